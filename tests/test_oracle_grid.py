@@ -1,0 +1,180 @@
+"""Pins of the oracle's grid builder (Secs. 3.2, 4.3, 4.4) on tiny grids:
+brute-force coordinate search for the neighbour list, an exact-cover check of
+the cell set, Morton order inside each level and the ghost/child relations."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle, NONE, SOLID, F_COARSE_GHOST, F_FINE_GHOST, F_BC_NEUMANN, F_BC_EQ
+from paper_2504_04465_amd import workloads as W
+
+
+def morton(D, x):
+    k = 0
+    for b in range(21):
+        for d in range(D):
+            k |= ((int(x[d]) >> b) & 1) << (D * b + d)
+    return k
+
+
+def tiny_cases():
+    r = np.random.default_rng(5)
+    cases = []
+    cases.append(("cavity", W.cavity(n=16, steps=1)))
+    cases.append(("shear3", W.shear(n=16, levels=3, steps=1)))
+    cases.append(("cyl", W.cylinder(scale=32, steps=1)))
+    cases.append(("sod", W.sod(nx=64, ny=8, steps=1)))
+    w3 = W.shear(n=8, levels=2, lattice="D3Q27", collision="RR", steps=1)
+    box = np.zeros((8, 8, 8), np.uint8)
+    box[3:6, 3:6, 3:6] = 1
+    w3.refine = [box]
+    sol = []
+    for l in range(2):
+        e = 8 << l
+        g = (np.arange(e) + 0.5) / (1 << l)
+        zz, yy, xx = np.meshgrid(g, g, g, indexing="ij")
+        sol.append((((xx - 1.5) ** 2 + (yy - 5.0) ** 2 + (zz - 5.0) ** 2) <= 1.0).astype(np.uint8))
+    w3.solid = sol
+    w3.faces = [W.Face("moving_wall", u=(0.05, 0, 0)), W.Face("neumann"), W.Face("wall"), W.Face("wall"),
+                W.Face("periodic"), W.Face("periodic")]
+    cases.append(("oct", w3))
+    # a random blob refinement on a periodic / wall mix
+    w = W.shear(n=24, levels=2, steps=1)
+    m = np.zeros((24, 24), np.uint8)
+    m[6:18, 4:20] = 1
+    m[10:14, 2:4] = 1
+    w.refine = [m]
+    w.faces = [W.Face("wall"), W.Face("wall"), W.Face("periodic"), W.Face("periodic"), W.Face(), W.Face()]
+    cases.append(("blob", w))
+    return cases
+
+
+@pytest.mark.parametrize("name,w", tiny_cases(), ids=[c[0] for c in tiny_cases()])
+def test_grid_brute_force(name, w):
+    o = Oracle.from_workload(w)
+    e = o.export()
+    D, Q = o.D, o.Q
+    coords, level, flags, nbr = e["coords"], e["level"], e["flags"], e["nbr"]
+    n = len(level)
+    L = w.n_levels
+    E = [[x << l for x in w.ext[:D]] for l in range(L)]
+    # level-major, Morton ascending within a level
+    assert np.all(np.diff(level) >= 0)
+    for l in range(L):
+        ks = [morton(D, coords[c]) for c in np.nonzero(level == l)[0]]
+        assert all(a < b for a, b in zip(ks, ks[1:]))
+    # exact cover: every finest point of the domain outside solids is covered
+    # once by the cells that are not fine ghosts
+    fine = L - 1
+    cover = np.zeros(tuple(E[fine][::-1]), np.int32)
+    for c in range(n):
+        if flags[c] & F_FINE_GHOST:
+            continue
+        s = 1 << (fine - level[c])
+        sl = tuple(slice(coords[c][d] * s, (coords[c][d] + 1) * s) for d in reversed(range(D)))
+        cover[sl] += 1
+    assert np.all(cover <= 1)
+    # uncovered points must lie in a solid cell of some level
+    any_solid = np.zeros_like(cover, dtype=bool)
+    for l in range(L):
+        if w.solid[l] is not None:
+            up = w.solid[l].astype(bool)
+            for ax in range(D):
+                up = np.repeat(up, 1 << (fine - l), axis=ax)
+            any_solid |= up
+    assert not np.any((cover == 0) & ~any_solid)
+    # ghost relations: a fine ghost's parent is a coarse ghost, a coarse
+    # ghost's children are fine ghosts
+    index = {(int(level[c]),) + tuple(int(v) for v in coords[c][:D]): c for c in range(n)}
+    child = e["child"]
+    ghosts = np.nonzero(flags & F_COARSE_GHOST)[0]
+    assert len(ghosts) == child.shape[0]
+    for k, g in enumerate(ghosts):
+        for o_ in range(1 << D):
+            off = [(o_ >> d) & 1 for d in range(D)]
+            key = (int(level[g]) + 1,) + tuple(2 * int(coords[g][d]) + off[d] for d in range(D))
+            assert child[k, o_] == index.get(key, -1)
+            if child[k, o_] >= 0:
+                assert flags[child[k, o_]] & F_FINE_GHOST
+    for c in np.nonzero(flags & F_FINE_GHOST)[0]:
+        key = (int(level[c]) - 1,) + tuple(int(v) // 2 for v in coords[c][:D])
+        assert key in index and flags[index[key]] & F_COARSE_GHOST
+    # neighbour list by brute-force scan over all cells of the level
+    periodic = [w.faces[2 * d].kind == "periodic" for d in range(D)]
+    for c in range(n):
+        l = int(level[c])
+        for i in range(1, Q):
+            src = [int(coords[c][d]) - int(o.c[i][d]) for d in range(D)]
+            out = []
+            for d in range(D):
+                if src[d] < 0 or src[d] >= E[l][d]:
+                    if periodic[d]:
+                        src[d] %= E[l][d]
+                    else:
+                        out.append(2 * d + (src[d] >= E[l][d]))
+            got = nbr[c, i - 1]
+            if out:
+                kinds = [w.faces[f].kind for f in out]
+                if "wall" in kinds:
+                    assert got == SOLID
+                elif "moving_wall" in kinds:
+                    assert got == -3 - min(f for f in out if w.faces[f].kind == "moving_wall")
+                else:
+                    assert got == NONE
+                continue
+            hit = index.get((l,) + tuple(src), None)
+            if hit is not None:
+                assert got == hit
+            else:
+                assert got in (NONE, SOLID)
+                if got == SOLID:
+                    assert w.solid[l] is not None and w.solid[l][tuple(reversed(src))] == 1
+    # bulk cells pull every population from a cell; neighbour links are
+    # mutual between cells whose populations stream both ways
+    for c in range(n):
+        if flags[c] & (F_COARSE_GHOST | F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ):
+            continue
+        assert np.all(nbr[c] != NONE)
+        for i in range(1, Q):
+            v = nbr[c, i - 1]
+            if v >= 0 and not flags[v] & (F_COARSE_GHOST | F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ):
+                assert nbr[v, o.opp[i] - 1] == c
+
+
+def test_coarse_ghost_unknowns_lie_inside_refined_region():
+    """Unknown coarse-ghost populations (no same-level source) are exactly the
+    ones whose source is inside the refined region beyond the strip."""
+    w = W.shear(n=16, levels=2, steps=1)
+    o = Oracle.from_workload(w)
+    e = o.export()
+    ref = w.refine[0]
+    for c in np.nonzero(e["flags"] & F_COARSE_GHOST)[0]:
+        x, y = e["coords"][c][:2]
+        for i in range(1, o.Q):
+            sx, sy = (x - o.c[i][0]) % 16, (y - o.c[i][1]) % 16
+            if e["nbr"][c, i - 1] == NONE:
+                assert ref[sy, sx] == 1
+
+
+def test_mask_validation():
+    w = W.shear(n=16, levels=3, steps=1, band=[(0.5, 1.0), (0.5, 0.75)])
+    with pytest.raises(RuntimeError, match="too close"):
+        Oracle.from_workload(w)
+    w = W.shear(n=16, levels=3, steps=1)
+    r1 = np.zeros_like(w.refine[1])
+    r1[0:4, :] = 1  # level-1 refinement outside the level-1 region
+    w.refine[1] = r1
+    with pytest.raises(RuntimeError, match="nested"):
+        Oracle.from_workload(w)
+
+
+def test_scheduler_counts():
+    """Sec. 4.5: level l runs 2^l times per coarse step (l = 0 coarsest)."""
+    w = W.shear(n=16, levels=3, steps=1)
+    o = Oracle.from_workload(w)
+    o.init_workload(w)
+    o.step(3)
+    upd, _, _ = o.counters()
+    npl = o.level_counts()
+    assert list(upd) == [3 * (1 << l) * int(npl[l]) for l in range(3)]
