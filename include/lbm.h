@@ -1,0 +1,226 @@
+/*
+ * lbm.h -- C-ABI of the MI355X refined-grid lattice Boltzmann library
+ * (liblbm.so).  The operations follow the problem statement of Coreixas &
+ * Latt, arXiv 2504.04465: a static cell-centred quad/octree given by level
+ * masks (Secs. 4.3-4.4), populations started at equilibrium from macroscopic
+ * fields (App. A.3), an asynchronous multi-level time loop (Sec. 4.5) with
+ * Rohde coalescence / uniform explosion at interfaces (Sec. 3.2, Eqs.
+ * coalescence and explosion_uniform), and macroscopic output.
+ *
+ * Conventions for every entry point:
+ *   - Levels are numbered 0 = coarsest; level l takes 2^l substeps per coarse
+ *     step (the paper numbers them the other way).
+ *   - Host pointers are owned by the caller and only accessed during the call.
+ *   - Device memory is owned by the library.  It is obtained through the
+ *     allocator given to lbm_create (or hipMalloc when none is given) and
+ *     released by lbm_destroy.
+ *   - Every call returns an lbm_status; no exception crosses the ABI.  The
+ *     text of the last error is available from lbm_last_error.
+ *   - Numerical failures inside lbm_step (NaN / Inf populations, Newton
+ *     iterations exhausted) are latched on the device and reported as
+ *     LBM_E_NUMERIC by the next synchronous call (lbm_sync, lbm_moments,
+ *     lbm_stats).  The latch stays set until lbm_init.
+ *   - Cells are in canonical order: level-major, Morton (Z-order) order inside
+ *     a level with x in the lowest key bit, then y, then z.
+ *   - Dense arrays are indexed with x fastest, then y, then z.
+ *   - One context per host thread; calls on a context are not re-entrant.
+ *     All device work of a context is enqueued on its stream.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_E_ARG = -1,         /* invalid argument                                  */
+  LBM_E_MASK = -2,        /* inconsistent level / solid masks or faces         */
+  LBM_E_NOMEM = -3,       /* allocation failed                                 */
+  LBM_E_DEVICE = -4,      /* HIP runtime error                                 */
+  LBM_E_STATE = -5,       /* call out of order (no grid, not initialised, ...) */
+  LBM_E_NUMERIC = -6,     /* NaN / Inf or Newton failure latched on device     */
+  LBM_E_UNSUPPORTED = -7  /* valid but unsupported combination                 */
+} lbm_status;
+
+/* lattices of App. A.1 (D3Q27 = D1Q3 x D1Q3 x D1Q3) */
+enum { LBM_D2Q9 = 0, LBM_D3Q27 = 1, LBM_D2Q21 = 2, LBM_D2Q37 = 3 };
+
+/* collision models of App. A.2:
+ *   BGK            Eq. CollisionStep with the polynomial equilibrium Eq. GenEq
+ *   RR             recursive regularisation, Eq. GenRegCollision
+ *   DDF_POLY       double distribution, fourth-order thermal polynomial
+ *                  equilibrium, g_eq of Eq. gEq, BGK on f and g (D2Q37)
+ *   DDF_NEWTON     double distribution, numerical equilibrium Eq. exponential
+ *                  solved by Newton on the eight constraints (D2Q21)
+ *   DDF_MLP        as DDF_NEWTON, multipliers predicted by the MLP only
+ *   DDF_MLP_NEWTON MLP prediction + one Newton step, full Newton wherever the
+ *                  constraint residual still exceeds fallback_tol            */
+enum { LBM_BGK = 0, LBM_RR = 1, LBM_DDF_POLY = 2, LBM_DDF_NEWTON = 3,
+       LBM_DDF_MLP = 4, LBM_DDF_MLP_NEWTON = 5 };
+
+/* population storage; collisions run in FP64 for LBM_FP64 and in FP32
+ * otherwise (Newton always in FP64) */
+enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_SHIFTED = 2 /* stores f_i - w_i */ };
+
+/* face boundary conditions (App. A.3) */
+enum { LBM_BC_PERIODIC = 0,    /* faces 2a and 2a+1 must both be periodic     */
+       LBM_BC_WALL = 1,        /* staircase bounce-back                        */
+       LBM_BC_MOVING_WALL = 2, /* Ladd velocity bounce-back, wall density 1   */
+       LBM_BC_NEUMANN = 3,     /* copy of the nearest fluid cell, B layers     */
+       LBM_BC_EQUILIBRIUM = 4  /* equilibrium Dirichlet, B layers              */ };
+
+/* node flags reported by lbm_grid_export */
+enum { LBM_F_COARSE_GHOST = 1, LBM_F_FINE_GHOST = 2, LBM_F_BC_NEUMANN = 4,
+       LBM_F_BC_EQ = 8, LBM_F_SPONGE = 16 };
+
+/* neighbour-list sentinels reported by lbm_grid_export */
+enum { LBM_NBR_NONE = -1, LBM_NBR_SOLID = -2 /* moving wall on face k: -3-k */ };
+
+typedef struct {
+  int lattice;             /* LBM_D2Q9 ...                                   */
+  int collision;           /* LBM_BGK ...                                    */
+  int storage;             /* LBM_FP64 ...                                   */
+  double nu_finest;        /* viscosity, lattice units of the finest level;
+                              <= 0: inviscid, tau = 1/2 on every level       */
+  double T0;               /* reference temperature (DDF), tau = nu/T0 + 1/2 */
+  double gamma;            /* specific heat ratio (DDF), Cv = 1/(gamma-1)    */
+  double sensor_A;         /* alpha on [0.1, 1) of Eq. shock_function        */
+  int sensor_on;           /* kinetic sensor, Eqs. DeltaAvg / shock_function */
+  int trace_equilibration; /* RR: bulk relaxation time one on the trace      */
+  double newton_tol;       /* stop when max_a |G_a| / rho <= newton_tol      */
+  double fallback_tol;     /* MLP_NEWTON: full Newton above this residual    */
+  int newton_max_it;       /* Newton iteration cap (failure latches NUMERIC) */
+  int lambda_warm_start;   /* 1: start Newton from the stored multipliers    */
+  int host_only;           /* 1: build the grid on the host only; no device
+                              call is made and init/step return LBM_E_STATE  */
+} lbm_params;
+
+typedef struct {
+  int kind;                /* LBM_BC_*                                        */
+  double rho, u[3], T;     /* moving-wall velocity, or equilibrium state     */
+  int extrapolate_rho;     /* equilibrium: take rho from the source cell     */
+  double sponge_sigma_max; /* pressure sponge strength at this face (Eq.
+                              relaxation_pressure, linear ramp)              */
+  double sponge_width;     /* ramp width in coarse cells                     */
+} lbm_face_bc;
+
+/* A mask restricted to a box [lo, lo + n) of one level's cell coordinates;
+ * values outside the box are 0.  data holds n[0]*n[1]*n[2] bytes, x fastest. */
+typedef struct {
+  const uint8_t *data;
+  int32_t lo[3];
+  int32_t n[3];
+} lbm_mask;
+
+typedef void *(*lbm_dev_alloc_fn)(size_t bytes, void *alloc_ctx);
+typedef void (*lbm_dev_free_fn)(void *ptr, void *alloc_ctx);
+
+/* Create a context.  dev_alloc / dev_free may be NULL (hipMalloc / hipFree are
+ * then used); hip_stream may be NULL (the null stream).  Errors: LBM_E_ARG
+ * for an unknown lattice / collision / storage or an unsupported combination
+ * (LBM_E_UNSUPPORTED), LBM_E_NOMEM. */
+lbm_status lbm_create(const lbm_params *params, lbm_dev_alloc_fn dev_alloc,
+                      lbm_dev_free_fn dev_free, void *alloc_ctx,
+                      void *hip_stream, lbm_ctx **out);
+
+/* Build the static tree and every derived table (Secs. 4.3-4.4): cells per
+ * level in canonical order, flags, the pull neighbour list (source x - xi_i
+ * on the same level), the coarse-ghost list with its child table and unknown
+ * populations, boundary layers, sponge strength.  refine[l-1] (l = 1 ..
+ * n_levels-1) has level l-1 resolution and marks the cells refined to level
+ * >= l; solid[l] (may be NULL, or have NULL data) marks level-l cells whose
+ * centre is inside a body.  faces: x-, x+, y-, y+, z-, z+ (z faces ignored in
+ * 2-D).  The grid is uploaded to the device unless host_only.  Errors:
+ * LBM_E_ARG (bad sizes), LBM_E_MASK (refinement not nested, interfaces closer
+ * than B cells of the coarser level, a solid body cutting an interface, a
+ * boundary layer overlapping an interface, unpaired periodic faces),
+ * LBM_E_NOMEM, LBM_E_DEVICE.  Replaces any previous grid and state. */
+lbm_status lbm_grid_build(lbm_ctx *ctx, int dim, const int32_t ext_coarse[3],
+                          int n_levels, const lbm_mask *refine,
+                          const lbm_mask *solid, const lbm_face_bc faces[6]);
+
+/* Cell counts; n_per_level has n_levels entries.  eq_fine_cells is
+ * sum_l n_l / 2^(L-1-l) (Sec. 7.3, "equivalent fine cells").  Any output
+ * pointer may be NULL. */
+lbm_status lbm_grid_info(lbm_ctx *ctx, int64_t *n_cells, int64_t *n_per_level,
+                         int64_t *n_coarse_ghosts, double *eq_fine_cells);
+
+/* Export the tables in canonical form (any pointer may be NULL):
+ * coords [n][3], level [n], flags [n], nbr [n][Q-1] (sentinels above),
+ * child [n_coarse_ghosts][2^D] (octant o = cx | cy<<1 | cz<<2, -1 missing),
+ * bc_src [n] (-1 for non-boundary cells). */
+lbm_status lbm_grid_export(lbm_ctx *ctx, int32_t *coords, int8_t *level,
+                           uint8_t *flags, int32_t *nbr, int32_t *child,
+                           int32_t *bc_src);
+
+/* Start every cell (ghosts included) at equilibrium (App. A.3): moments is a
+ * host array [n_mom][n_cells], n_mom = 1 + D (+1 temperature for DDF):
+ * rho, u_x, u_y, (u_z), (T).  D2Q21 multipliers come from a cold Newton.
+ * Clears the numeric latch and the counters.  Synchronous. */
+lbm_status lbm_init(lbm_ctx *ctx, const double *moments);
+
+/* Enqueue n coarse steps: per coarse step 2^(L-1) finest substeps; at each
+ * substep the active levels run coarsest first (coupling then collide-and-
+ * stream, Sec. 4.5).  Does not synchronise. */
+lbm_status lbm_step(lbm_ctx *ctx, int64_t n_coarse_steps);
+
+/* Replace the values of a face (same kind), e.g. an inlet Mach ramp; takes
+ * effect for work enqueued afterwards. */
+lbm_status lbm_set_face_bc(lbm_ctx *ctx, int face, const lbm_face_bc *bc);
+
+/* Macroscopic fields of the state at the synchronisation point (pre-
+ * collision populations, coarse ghosts with coalesced unknowns; fine ghosts
+ * are NaN), written to the host array out [n_mom][n_cells].  Synchronous. */
+lbm_status lbm_moments(lbm_ctx *ctx, double *out);
+
+/* As lbm_moments but into device memory out_dev [n_mom][n_cells]; enqueued
+ * on the context stream, no synchronisation. */
+lbm_status lbm_moments_device(lbm_ctx *ctx, double *out_dev);
+
+typedef struct {
+  double mass, momentum[3], energy; /* sum over non-fine-ghost cells of
+                                       2^(-D l) sum_i (1, xi, |xi|^2/2) f_i
+                                       (+ g/2 for DDF), FP64              */
+  int64_t updates[8];               /* cell updates per level             */
+  int64_t newton_calls, newton_iterations, newton_failures;
+  int64_t mlp_fallbacks, nonfinite_cells;
+  int64_t coarse_steps;
+} lbm_stats;
+
+/* Conservation sums and counters; synchronous. */
+lbm_status lbm_stats_get(lbm_ctx *ctx, lbm_stats *out);
+
+/* Wait for all enqueued work; reports a latched numeric failure. */
+lbm_status lbm_sync(lbm_ctx *ctx);
+
+/* Kernel timing: when enabled, every collide-and-stream launch is bracketed
+ * by HIP events on the context stream.  lbm_profile_read synchronises and
+ * returns, for level l, the number of timed launches, their summed duration
+ * in milliseconds, and the algorithmic bytes one update of that level moves
+ * (read + write of the populations, neighbour indices and multipliers). */
+lbm_status lbm_profile_enable(lbm_ctx *ctx, int on);
+lbm_status lbm_profile_read(lbm_ctx *ctx, int level, int64_t *launches,
+                            double *total_ms, double *bytes_per_update);
+
+/* Checkpoint: raw state in canonical cell order, FP64 on the host:
+ * f [Q][n_cells] (pre-collision, as at the synchronisation point),
+ * g [Q][n_cells] (DDF only, else may be NULL), lambda [8][n_cells] (D2Q21
+ * only, else may be NULL).  lbm_set_state restores such a state. */
+lbm_status lbm_get_state(lbm_ctx *ctx, double *f, double *g, double *lambda);
+lbm_status lbm_set_state(lbm_ctx *ctx, const double *f, const double *g,
+                         const double *lambda);
+
+const char *lbm_last_error(const lbm_ctx *ctx);
+void lbm_destroy(lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -149,22 +149,30 @@ class Oracle:
             raise RuntimeError(f"oracle error {rc}: {self._L.ol_error(self.h).decode()}")
 
     def grid(self, dim, ext, n_levels, refine, solid, faces):
+        """refine[l] / solid[l]: dense uint8 arrays of level l (shape (Ey, Ex)
+        or (Ez, Ey, Ex)), or window objects with a dense(extent) method."""
         e = np.array(list(ext) + [1] * (3 - len(ext)), np.int32)
-        self._keep = [np.ascontiguousarray(r, dtype=np.uint8) for r in refine]
+
+        def dense(m, level):
+            if m is None:
+                return None
+            extent = tuple(int(x) << level for x in ext[:dim])
+            if hasattr(m, "dense"):
+                return m.dense(extent)
+            return np.ascontiguousarray(m, dtype=np.uint8)
+
+        self._keep = [dense(r, l) for l, r in enumerate(refine)]
         rp = (C.c_void_p * max(1, len(self._keep)))(*[_ptr(a) for a in self._keep])
-        sol = [None if s is None else np.ascontiguousarray(s, dtype=np.uint8) for s in solid]
-        self._keep_s = sol
         sp = None
-        if any(s is not None for s in sol):
-            sol = [np.zeros(1, np.uint8) if s is None else s for s in sol]
-            sol2 = []
-            for l, s in enumerate(sol):
-                if s.size == 1:
-                    shape = tuple(x << l for x in ext[:dim])[::-1]
-                    s = np.zeros(shape, np.uint8)
-                sol2.append(s)
-            self._keep_s = sol2
-            sp = (C.c_void_p * len(sol2))(*[_ptr(a) for a in sol2])
+        if solid is not None and any(s is not None for s in solid):
+            sol = []
+            for l in range(n_levels):
+                s = dense(solid[l], l) if l < len(solid) else None
+                if s is None:
+                    s = np.zeros(tuple(int(x) << l for x in ext[:dim])[::-1], np.uint8)
+                sol.append(s)
+            self._keep_s = sol
+            sp = (C.c_void_p * len(sol))(*[_ptr(a) for a in sol])
         fa = (Face * 6)(*[make_face(f) for f in faces])
         self._check(self._L.ol_grid(self.h, dim, _ptr(e), n_levels, rp, sp, fa))
         self.n = self._L.ol_n_cells(self.h)

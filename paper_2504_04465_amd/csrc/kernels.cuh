@@ -1,0 +1,947 @@
+// kernels.cuh -- HIP kernels of the refined-grid lattice Boltzmann update for
+// gfx950, templated on lattice, collision model and population storage.
+//
+// Data layout (HBM): populations are structure-of-arrays, f[i * stride + c],
+// double buffered per level; each level's newest buffer holds post-collision
+// populations (the pull of the next update streams them).  The pull source
+// of population i of cell c is nbr[(i-1) * stride + c]:
+//   >= vbase : a coalesced slot of a coarse ghost (unknown population),
+//   >= 0     : a cell of the same level (the cell itself when the paper's
+//              rule keeps the own value),
+//   -1       : bounce-back on a wall or solid,
+//   -2 - k   : Ladd bounce-back on the moving wall of face k.
+// One thread updates one cell; a 256-thread block holds 4 wavefronts of 64
+// Z-ordered cells, so a wavefront is a 8x8 (2-D) or 4x4x4 (3-D) brick.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "grid_builder.h"
+#include "lattice.h"
+#include "ops.h"
+
+namespace lbm {
+
+constexpr int BLOCK = 256;
+
+// ---------------------------------------------------------------------------
+// storage traits: FP64, FP32, FP16 holding f_i - w_i (compute in FP32)
+// ---------------------------------------------------------------------------
+template <class S>
+struct Sto;
+template <>
+struct Sto<double> {
+  using C = double;
+  __device__ static C ld(const double *p, int64_t k, double) { return p[k]; }
+  __device__ static void st(double *p, int64_t k, C v, double) { p[k] = v; }
+};
+template <>
+struct Sto<float> {
+  using C = float;
+  __device__ static C ld(const float *p, int64_t k, double) { return p[k]; }
+  __device__ static void st(float *p, int64_t k, C v, double) { p[k] = v; }
+};
+template <>
+struct Sto<__half> {
+  using C = float;
+  __device__ static C ld(const __half *p, int64_t k, double w) {
+    return __half2float(p[k]) + (float)w;
+  }
+  __device__ static void st(__half *p, int64_t k, C v, double w) {
+    p[k] = __float2half_rn(v - (float)w);
+  }
+};
+
+// Blocks are dealt to the 8 XCDs round-robin; remap so that each XCD works
+// on one contiguous range of Z-ordered cells and its L2 sees the neighbours.
+__device__ inline int64_t xcd_block() {
+  const uint32_t nb = gridDim.x, b = blockIdx.x;
+  const uint32_t q = nb >> 3, r = nb & 7u, x = b & 7u, loc = b >> 3;
+  return (int64_t)x * q + (x < r ? x : r) + loc;
+}
+
+template <int W, class T>
+__device__ inline T group_sum(T v) {
+#pragma unroll
+  for (int m = 1; m < W; m <<= 1) v += __shfl_xor(v, m, W);
+  return v;
+}
+
+template <class L>
+__device__ constexpr int cx_(int i, int d) {
+  return d == 0 ? L::S.v[i].x : d == 1 ? L::S.v[i].y : L::S.v[i].z;
+}
+
+// velocity of moving wall k projected on xi_i, selected without indexing the
+// argument block dynamically
+template <class L>
+__device__ inline double wall_dot(const double (&uw)[6][3], int k, int i) {
+  double r = 0.0;
+#pragma unroll
+  for (int f = 0; f < 6; ++f)
+    if (f == k) r = cx_<L>(i, 0) * uw[f][0] + cx_<L>(i, 1) * uw[f][1] + cx_<L>(i, 2) * uw[f][2];
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// pull of one population; PRE: the buffer still holds pre-collision values
+// (after initialisation or a state restore), so only coalesced slots move
+// ---------------------------------------------------------------------------
+template <class L, class S, bool PRE>
+__device__ inline typename Sto<S>::C pull_f(const S *fin, const int32_t *nbr, int64_t stride,
+                                            int64_t vbase, int64_t c, int i,
+                                            const double (&uw)[6][3], double cs2w) {
+  using C = typename Sto<S>::C;
+  const int32_t s = nbr[(int64_t)(i - 1) * stride + c];
+  if (PRE) {
+    const int64_t src = ((int64_t)s >= vbase) ? (int64_t)s : c;
+    return Sto<S>::ld(fin, (int64_t)i * stride + src, L::S.w[i]);
+  }
+  if (s >= 0) return Sto<S>::ld(fin, (int64_t)i * stride + s, L::S.w[i]);
+  const int io = L::S.opp[i];
+  C v = Sto<S>::ld(fin, (int64_t)io * stride + c, L::S.w[io]);
+  if (s <= -2) v += (C)(2.0 * L::S.w[i] * wall_dot<L>(uw, -2 - s, i) / cs2w);
+  return v;
+}
+
+template <class L, class S, bool PRE>
+__device__ inline typename Sto<S>::C pull_g(const S *gin, const int32_t *nbr, int64_t stride,
+                                            int64_t vbase, int64_t c, int i) {
+  const int32_t s = nbr[(int64_t)(i - 1) * stride + c];
+  if (PRE) {
+    const int64_t src = ((int64_t)s >= vbase) ? (int64_t)s : c;
+    return Sto<S>::ld(gin, (int64_t)i * stride + src, 0.0);
+  }
+  if (s >= 0) return Sto<S>::ld(gin, (int64_t)i * stride + s, 0.0);
+  return Sto<S>::ld(gin, (int64_t)L::S.opp[i] * stride + c, 0.0);
+}
+
+template <class L, class S, bool PRE, bool DDF>
+__device__ inline void gather(const S *fin, const S *gin, const int32_t *nbr, int64_t stride,
+                              int64_t vbase, int64_t c, const double (&uw)[6][3], double cs2w,
+                              typename Sto<S>::C *f, typename Sto<S>::C *g) {
+  f[0] = Sto<S>::ld(fin, c, L::S.w[0]);
+  if (DDF) g[0] = Sto<S>::ld(gin, c, 0.0);
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) {
+    f[i] = pull_f<L, S, PRE>(fin, nbr, stride, vbase, c, i, uw, cs2w);
+    if (DDF) g[i] = pull_g<L, S, PRE>(gin, nbr, stride, vbase, c, i);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// product lattices (D2Q9, D3Q27): equilibrium and recursive regularisation
+// on the Hermite basis {1, xi, xi^2 - cs2}^D
+// ---------------------------------------------------------------------------
+template <class L, class C>
+__device__ inline void equilibrium_product(C rho, const C *u, C *feq) {
+  constexpr C a1 = (C)(1.0 / L::cs2), a2 = (C)((1.0 - L::cs2) / (2.0 * L::cs2 * L::cs2));
+  constexpr C a0 = (C)(1.0 / (2.0 * L::cs2));
+  C p[3][3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const C ud = d < L::D ? u[d] : (C)0;
+    const C q = ud * ud;
+    p[d][1] = (C)1 - a0 * q;
+    p[d][2] = (C)1 + a1 * ud + a2 * q;
+    p[d][0] = (C)1 - a1 * ud + a2 * q;
+  }
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    C v = (C)L::S.w[i] * rho;
+#pragma unroll
+    for (int d = 0; d < L::D; ++d) v *= p[d][cx_<L>(i, d) + 1];
+    feq[i] = v;
+  }
+}
+
+template <class C>
+__device__ inline C upow(C x, int e) {
+  return e <= 0 ? (C)1 : (e == 1 ? x : x * x);
+}
+
+// f*_i = w_i sum_m H_m(xi_i) a*_m / (m! cs2^|m|), a*_m = a_eq,m + k a_neq,m,
+// with a_neq,m the closed pair sum that solves the non-equilibrium
+// recursion; evaluated by sum factorisation one axis at a time.
+template <class L, class C>
+__device__ inline void rr_product(C *f, C rho, C rhop, const C *u, C (&P)[3][3], C k,
+                                  bool trace_eq) {
+  constexpr int D = L::D;
+  constexpr C cs2 = (C)L::cs2, ics2 = (C)(1.0 / L::cs2);
+  C A[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      A[a][b] = (a < D && b < D) ? P[a][b] - rho * u[a] * u[b] - (a == b ? rho * cs2 : (C)0) : (C)0;
+  if (trace_eq) {
+    C tr = (C)0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) tr += A[a][a];
+    tr *= (C)(1.0 / D);
+#pragma unroll
+    for (int a = 0; a < D; ++a) A[a][a] -= tr;
+  }
+  C uu[3] = {u[0], u[1], D == 3 ? u[2] : (C)0};
+  C b[3][3][3];
+#pragma unroll
+  for (int mx = 0; mx < 3; ++mx)
+#pragma unroll
+    for (int my = 0; my < 3; ++my)
+#pragma unroll
+      for (int mz = 0; mz < 3; ++mz) {
+        if (D == 2 && mz > 0) { b[mx][my][mz] = (C)0; continue; }
+        const int m[3] = {mx, my, mz};
+        C aeq = rhop * upow(uu[0], mx) * upow(uu[1], my) * upow(uu[2], mz);
+        C an = (C)0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          if (m[d] == 2) {
+            C t = A[d][d];
+#pragma unroll
+            for (int e = 0; e < 3; ++e)
+              if (e != d) t *= upow(uu[e], m[e]);
+            an += t;
+          }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int e = d + 1; e < 3; ++e) {
+            if (m[d] >= 1 && m[e] >= 1) {
+              C t = (C)(m[d] * m[e]) * A[d][e];
+#pragma unroll
+              for (int h = 0; h < 3; ++h) t *= upow(uu[h], m[h] - (h == d) - (h == e));
+              an += t;
+            }
+          }
+        C scale = (C)1;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) scale *= (m[d] == 2 ? (C)0.5 * ics2 * ics2 : (m[d] == 1 ? ics2 : (C)1));
+        b[mx][my][mz] = (aeq + k * an) * scale;
+      }
+  // h_0 = 1, h_1 = xi, h_2 = xi^2 - cs2 evaluated at xi in {-1, 0, 1}
+  C T1[3][3][3];
+#pragma unroll
+  for (int mx = 0; mx < 3; ++mx)
+#pragma unroll
+    for (int my = 0; my < 3; ++my)
+#pragma unroll
+      for (int iz = 0; iz < 3; ++iz) {
+        if (D == 2) { T1[mx][my][iz] = b[mx][my][0]; continue; }
+        const C xi = (C)(iz - 1);
+        T1[mx][my][iz] = b[mx][my][0] + xi * b[mx][my][1] + (xi * xi - cs2) * b[mx][my][2];
+      }
+  C T2[3][3][3];
+#pragma unroll
+  for (int mx = 0; mx < 3; ++mx)
+#pragma unroll
+    for (int iy = 0; iy < 3; ++iy)
+#pragma unroll
+      for (int iz = 0; iz < 3; ++iz) {
+        const C xi = (C)(iy - 1);
+        T2[mx][iy][iz] = T1[mx][0][iz] + xi * T1[mx][1][iz] + (xi * xi - cs2) * T1[mx][2][iz];
+      }
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    const int ix = cx_<L>(i, 0) + 1, iy = cx_<L>(i, 1) + 1, iz = D == 3 ? cx_<L>(i, 2) + 1 : 0;
+    const C xi = (C)(ix - 1);
+    const C v = T2[0][iy][iz] + xi * T2[1][iy][iz] + (xi * xi - cs2) * T2[2][iy][iz];
+    f[i] = (C)L::S.w[i] * v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// D2Q37 fourth-order thermal equilibrium: Hermite coefficients of a
+// Maxwellian of temperature T on the cs2 basis, a_m = rho prod_d A_{m_d},
+// A_0..4 = 1, u, u^2+th, u^3+3 th u, u^4+6 th u^2+3 th^2, th = T - cs2
+// ---------------------------------------------------------------------------
+constexpr double h1c(int n, double x, double cs2) {
+  return n == 0 ? 1.0
+       : n == 1 ? x
+       : n == 2 ? x * x - cs2
+       : n == 3 ? (x * x - 3.0 * cs2) * x
+                : x * x * x * x - 6.0 * cs2 * x * x + 3.0 * cs2 * cs2;
+}
+constexpr double fact_c(int n) { return n <= 1 ? 1.0 : n * fact_c(n - 1); }
+constexpr double pow_c(double x, int n) { return n == 0 ? 1.0 : x * pow_c(x, n - 1); }
+
+template <int Q>
+struct ThermalTable {
+  int mx[15], my[15];
+  double hw[Q][15];
+};
+
+template <class L>
+constexpr ThermalTable<L::Q> make_thermal() {
+  ThermalTable<L::Q> t{};
+  int k = 0;
+  for (int n = 0; n <= 4; ++n)
+    for (int my = 0; my <= n; ++my) {
+      t.mx[k] = n - my;
+      t.my[k] = my;
+      ++k;
+    }
+  for (int i = 0; i < L::Q; ++i)
+    for (int k2 = 0; k2 < 15; ++k2) {
+      const int a = t.mx[k2], b = t.my[k2];
+      t.hw[i][k2] = L::S.w[i] * h1c(a, L::S.v[i].x, L::cs2) * h1c(b, L::S.v[i].y, L::cs2) /
+                    (fact_c(a) * fact_c(b) * pow_c(L::cs2, a + b));
+    }
+  return t;
+}
+
+template <class L>
+struct Thermal {
+  static constexpr ThermalTable<L::Q> T = make_thermal<L>();
+};
+
+template <class L, class C>
+__device__ inline void equilibrium_thermal(C rho, const C *u, C T, C *feq) {
+  const C th = T - (C)L::cs2;
+  C A[2][5];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    const C x = u[d], x2 = x * x;
+    A[d][0] = (C)1;
+    A[d][1] = x;
+    A[d][2] = x2 + th;
+    A[d][3] = x * (x2 + (C)3 * th);
+    A[d][4] = x2 * x2 + (C)6 * th * x2 + (C)3 * th * th;
+  }
+  C a[15];
+#pragma unroll
+  for (int k = 0; k < 15; ++k) a[k] = rho * A[0][Thermal<L>::T.mx[k]] * A[1][Thermal<L>::T.my[k]];
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    C v = (C)0;
+#pragma unroll
+    for (int k = 0; k < 15; ++k) {
+      const double h = Thermal<L>::T.hw[i][k];
+      if (h != 0.0) v += (C)h * a[k];
+    }
+    feq[i] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// numerical (entropy-maximising) equilibrium, D2Q21: f_eq = rho exp(-(1 +
+// lambda . m_i)) under the eight moment constraints; Newton with a Cholesky
+// step and backtracking on ||G||_2, FP64
+// ---------------------------------------------------------------------------
+template <class L>
+__device__ constexpr double mvec(int i, int a) {
+  const double x = L::S.v[i].x, y = L::S.v[i].y, n2 = x * x + y * y;
+  return a == 0 ? 1.0 : a == 1 ? x : a == 2 ? y : a == 3 ? x * x : a == 4 ? x * y : a == 5 ? y * y
+       : a == 6 ? x * n2 : y * n2;
+}
+
+template <class L>
+__device__ inline void expo_residual(const double *lam, const double *M, double *e, double *G) {
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    double s = 1.0;
+#pragma unroll
+    for (int a = 0; a < NLAM; ++a)
+      if (mvec<L>(i, a) != 0.0) s += lam[a] * mvec<L>(i, a);
+    e[i] = exp(-s);
+  }
+#pragma unroll
+  for (int a = 0; a < NLAM; ++a) {
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i)
+      if (mvec<L>(i, a) != 0.0) acc += e[i] * mvec<L>(i, a);
+    G[a] = acc - M[a];
+  }
+}
+
+__device__ inline double nrm2_8(const double *G) {
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < NLAM; ++a) s += G[a] * G[a];
+  return s;
+}
+
+__device__ inline double nrmmax_8(const double *G) {
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < NLAM; ++a) s = fmax(s, fabs(G[a]));
+  return s;
+}
+
+template <class L>
+__device__ inline void targets(double ux, double uy, double T, double *M) {
+  const double uu = ux * ux + uy * uy;
+  M[0] = 1.0;
+  M[1] = ux;
+  M[2] = uy;
+  M[3] = ux * ux + T;
+  M[4] = ux * uy;
+  M[5] = uy * uy + T;
+  M[6] = ux * (uu + 4.0 * T);
+  M[7] = uy * (uu + 4.0 * T);
+}
+
+// one Newton step from (lam, G, e): solves (sum e m m^T) d = G by Cholesky
+// and backtracks; returns false if the matrix is not positive definite
+template <class L>
+__device__ inline bool newton_step(double *lam, double *G, double *e, const double *M) {
+  double H[NLAM * (NLAM + 1) / 2];
+#pragma unroll
+  for (int a = 0; a < NLAM; ++a)
+#pragma unroll
+    for (int b = 0; b <= a; ++b) {
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < L::Q; ++i) {
+        const double mm = mvec<L>(i, a) * mvec<L>(i, b);
+        if (mm != 0.0) acc += e[i] * mm;
+      }
+      H[a * (a + 1) / 2 + b] = acc;
+    }
+  // in-place Cholesky, packed lower triangle
+#pragma unroll
+  for (int j = 0; j < NLAM; ++j) {
+    double d = H[j * (j + 1) / 2 + j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= H[j * (j + 1) / 2 + k] * H[j * (j + 1) / 2 + k];
+    if (!(d > 0.0)) return false;
+    const double ljj = sqrt(d);
+    H[j * (j + 1) / 2 + j] = ljj;
+    const double inv = 1.0 / ljj;
+#pragma unroll
+    for (int i = j + 1; i < NLAM; ++i) {
+      double s = H[i * (i + 1) / 2 + j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) s -= H[i * (i + 1) / 2 + k] * H[j * (j + 1) / 2 + k];
+      H[i * (i + 1) / 2 + j] = s * inv;
+    }
+  }
+  double y[NLAM], dlt[NLAM];
+#pragma unroll
+  for (int i = 0; i < NLAM; ++i) {
+    double s = G[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) s -= H[i * (i + 1) / 2 + k] * y[k];
+    y[i] = s / H[i * (i + 1) / 2 + i];
+  }
+#pragma unroll
+  for (int i = NLAM - 1; i >= 0; --i) {
+    double s = y[i];
+#pragma unroll
+    for (int k = i + 1; k < NLAM; ++k) s -= H[k * (k + 1) / 2 + i] * dlt[k];
+    dlt[i] = s / H[i * (i + 1) / 2 + i];
+  }
+  const double n0 = nrm2_8(G);
+  double alpha = 1.0, trial[NLAM], Gt[NLAM], et[L::Q];
+  for (int h = 0; h <= 30; ++h) {
+#pragma unroll
+    for (int a = 0; a < NLAM; ++a) trial[a] = lam[a] + alpha * dlt[a];
+    expo_residual<L>(trial, M, et, Gt);
+    if (nrm2_8(Gt) < n0 || h == 30) break;
+    alpha *= 0.5;
+  }
+#pragma unroll
+  for (int a = 0; a < NLAM; ++a) {
+    lam[a] = trial[a];
+    G[a] = Gt[a];
+  }
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) e[i] = et[i];
+  return true;
+}
+
+// returns the iteration count, or -1 when not converged
+template <class L>
+__device__ inline int newton_solve(double ux, double uy, double T, double *lam, double tol,
+                                   int max_it, double *e) {
+  double M[NLAM], G[NLAM];
+  targets<L>(ux, uy, T, M);
+  expo_residual<L>(lam, M, e, G);
+  for (int it = 0; it <= max_it; ++it) {
+    if (nrmmax_8(G) <= tol) return it;
+    if (it == max_it) break;
+    if (!newton_step<L>(lam, G, e, M)) return -1;
+  }
+  return -1;
+}
+
+// ---------------------------------------------------------------------------
+// kinetic sensor, Eqs. DeltaAvg and shock_function
+// ---------------------------------------------------------------------------
+template <class L, class C>
+__device__ inline C sensor_alpha(const C *f, const C *feq, C tau, C A) {
+  constexpr C tiny = sizeof(C) == 8 ? (C)1e-300 : (C)1e-30;
+  C eps = (C)0;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) eps += fabs(f[i] - feq[i]) / fmax(fabs(feq[i]), tiny);
+  eps *= (C)(1.0 / L::Q);
+  return eps < (C)0.01 ? (C)1 : eps < (C)0.1 ? (C)1.05 : eps < (C)1 ? A : (C)1 / tau;
+}
+
+// ---------------------------------------------------------------------------
+// macroscopic moments of a cell
+// ---------------------------------------------------------------------------
+template <class L, class C, bool DDF>
+__device__ inline void cell_moments(const C *f, const C *g, C Cv, C &rho, C (&u)[3], C &T) {
+  rho = (C)0;
+  C j[3] = {(C)0, (C)0, (C)0};
+  C e2 = (C)0, gs = (C)0;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    rho += f[i];
+#pragma unroll
+    for (int d = 0; d < L::D; ++d)
+      if (cx_<L>(i, d) != 0) j[d] += (C)cx_<L>(i, d) * f[i];
+    if (DDF) {
+      const int n2 = cx_<L>(i, 0) * cx_<L>(i, 0) + cx_<L>(i, 1) * cx_<L>(i, 1) + cx_<L>(i, 2) * cx_<L>(i, 2);
+      if (n2 != 0) e2 += (C)n2 * f[i];
+      gs += g[i];
+    }
+  }
+  const C inv = (C)1 / rho;
+  C uu = (C)0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    u[d] = d < L::D ? j[d] * inv : (C)0;
+    uu += u[d] * u[d];
+  }
+  T = DDF ? (e2 + gs - rho * uu) / ((C)2 * rho * Cv) : (C)0;
+}
+
+// equilibrium of any model at a macroscopic state; Newton family updates lam
+template <class L, int COLL, class C>
+__device__ inline int equilibrium_any(C rho, const C *u, C T, const PhysArgs &ph, double *lam,
+                                      bool warm, C *feq, C *geq) {
+  int it = 0;
+  if constexpr (COLL == COLL_BGK || COLL == COLL_RR) {
+    equilibrium_product<L, C>(rho, u, feq);
+  } else if constexpr (COLL == COLL_DDF_POLY) {
+    equilibrium_thermal<L, C>(rho, u, T, feq);
+  } else {
+    if (!warm)
+#pragma unroll
+      for (int a = 0; a < NLAM; ++a) lam[a] = 0.0;
+    double e[L::Q];
+    it = newton_solve<L>((double)u[0], (double)u[1], (double)T, lam, ph.newton_tol, ph.newton_max_it, e);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) feq[i] = (C)((double)rho * e[i]);
+  }
+  if constexpr (COLL >= COLL_DDF_POLY) {
+    const C k = ((C)2 * (C)ph.Cv - (C)L::D) * T;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) geq[i] = k * feq[i];
+  }
+  return it;
+}
+
+__device__ inline void count_add(unsigned long long *ctr, int which, unsigned long long v) {
+  if (v) atomicAdd(ctr + which, v);
+}
+
+// ---------------------------------------------------------------------------
+// collide and stream (pull) for the cells [begin, begin + count) of a level
+// ---------------------------------------------------------------------------
+template <class L, int COLL, class S, bool PRE>
+__global__ void __launch_bounds__(BLOCK) k_collide(const KArgs a) {
+  using C = typename Sto<S>::C;
+  constexpr bool DDF = COLL >= COLL_DDF_POLY;
+  constexpr int Q = L::Q;
+  const int64_t t = xcd_block() * BLOCK + threadIdx.x;
+  if (t >= a.count) return;
+  const int64_t c = a.begin + t;
+  const int64_t stride = a.stride;
+  const S *fin = (const S *)a.fin;
+  const S *gin = (const S *)a.gin;
+  C f[Q];
+  C g[DDF ? Q : 1];
+  gather<L, S, PRE, DDF>(fin, gin, a.nbr, stride, a.vbase, c, a.ph.uw, a.ph.cs2w, f, g);
+  const uint8_t fl = a.flags[c];
+  if (!(fl & (F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ))) {
+    C rho, u[3], T;
+    cell_moments<L, C, DDF>(f, g, (C)a.ph.Cv, rho, u, T);
+    C rhop = rho;
+    if (fl & F_SPONGE) {
+      const C s = (C)a.sigma[c];
+      rhop = rho * ((C)1 - s) + s * (C)a.rho_inf[c];
+    }
+    if (!(rho > (C)0) || !isfinite(rho)) count_add(a.counters, CNT_NONFINITE, 1);
+    if constexpr (COLL == COLL_BGK) {
+      C feq[Q];
+      equilibrium_product<L, C>(rhop, u, feq);
+      const C om = (C)(1.0 / a.ph.tau);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) f[i] = f[i] - om * (f[i] - feq[i]);
+    } else if constexpr (COLL == COLL_RR) {
+      C P[3][3];
+#pragma unroll
+      for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y) P[x][y] = (C)0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+#pragma unroll
+        for (int x = 0; x < L::D; ++x)
+#pragma unroll
+          for (int y = x; y < L::D; ++y) {
+            const int cc = cx_<L>(i, x) * cx_<L>(i, y);
+            if (cc != 0) P[x][y] += (C)cc * f[i];
+          }
+#pragma unroll
+      for (int x = 0; x < L::D; ++x)
+#pragma unroll
+        for (int y = 0; y < x; ++y) P[x][y] = P[y][x];
+      rr_product<L, C>(f, rho, rhop, u, P, (C)(1.0 - 1.0 / a.ph.tau), a.ph.trace_eq != 0);
+    } else {
+      C feq[Q], geq[Q];
+      double lam[NLAM];
+      if constexpr (COLL >= COLL_DDF_NEWTON) {
+#pragma unroll
+        for (int k = 0; k < NLAM; ++k) lam[k] = (double)a.lam[(int64_t)k * stride + c];
+      }
+      const int it = equilibrium_any<L, COLL, C>(rhop, u, T, a.ph, lam, a.ph.warm != 0, feq, geq);
+      if constexpr (COLL >= COLL_DDF_NEWTON) {
+        count_add(a.counters, CNT_NEWTON_CALLS, 1);
+        if (it < 0) count_add(a.counters, CNT_NEWTON_FAIL, 1);
+        else count_add(a.counters, CNT_NEWTON_ITERS, (unsigned long long)it);
+#pragma unroll
+        for (int k = 0; k < NLAM; ++k) a.lam[(int64_t)k * stride + c] = (float)lam[k];
+      }
+      C te = (C)a.ph.tau;
+      if (a.ph.sensor_on) te *= sensor_alpha<L, C>(f, feq, te, (C)a.ph.sensor_A);
+      const C om = (C)1 / te;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        f[i] = f[i] - om * (f[i] - feq[i]);
+        g[i] = g[i] - om * (g[i] - geq[i]);
+      }
+    }
+  }
+  S *fout = (S *)a.fout;
+  S *gout = (S *)a.gout;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    Sto<S>::st(fout, (int64_t)i * stride + c, f[i], L::S.w[i]);
+    if (DDF) Sto<S>::st(gout, (int64_t)i * stride + c, g[i], 0.0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// coalescence (Eq. coalescence): 2^D lanes per coarse ghost, one per child;
+// each lane pulls the child's population as the fine level's next update
+// would, the lanes of a ghost are summed with wavefront shuffles
+// ---------------------------------------------------------------------------
+template <class L, class S, bool PRE, bool DDF, bool LAM>
+__global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
+  using C = typename Sto<S>::C;
+  constexpr int NCH = 1 << L::D;
+  const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int64_t gl = t / NCH;
+  const bool valid = gl < a.count;
+  const int64_t gk = a.g0 + gl;
+  const int32_t ch = valid ? a.child[gk * NCH + (t % NCH)] : -1;
+  const uint64_t mask = valid ? a.unknown[gk] : 0ull;
+  const bool lead = valid && (t % NCH) == 0;
+  const C nf = group_sum<NCH, C>(ch >= 0 ? (C)1 : (C)0);
+  const S *fin = (const S *)a.fin_child;
+  const S *gin = (const S *)a.gin_child;
+  S *fout = (S *)a.fout_coarse;
+  S *gout = (S *)a.gout_coarse;
+  const int64_t slot = a.vbase + gk;
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) {
+    const bool need = (mask >> i) & 1ull;
+    C v = (C)0, vg = (C)0;
+    if (need && ch >= 0) {
+      v = pull_f<L, S, PRE>(fin, a.nbr, a.stride, a.vbase, ch, i, a.uw, a.cs2w);
+      if (DDF) vg = pull_g<L, S, PRE>(gin, a.nbr, a.stride, a.vbase, ch, i);
+    }
+    v = group_sum<NCH, C>(v);
+    if (DDF) vg = group_sum<NCH, C>(vg);
+    if (lead && need) {
+      Sto<S>::st(fout, (int64_t)i * a.stride + slot, v / nf, L::S.w[i]);
+      if (DDF) Sto<S>::st(gout, (int64_t)i * a.stride + slot, vg / nf, 0.0);
+    }
+  }
+  if (LAM) {
+    const int64_t G = valid ? a.ghost_cell[gk] : 0;
+#pragma unroll
+    for (int k = 0; k < NLAM; ++k) {
+      double v = ch >= 0 ? (double)a.lam[(int64_t)k * a.stride + ch] : 0.0;
+      v = group_sum<NCH, double>(v);
+      if (lead) a.lam[(int64_t)k * a.stride + G] = (float)(v / (double)nf);
+    }
+  }
+}
+
+// uniform explosion (Eq. explosion_uniform): children take every
+// post-collision population of their coarse ghost (raw copy of storage)
+template <class L, class S, bool DDF, bool LAM>
+__global__ void __launch_bounds__(BLOCK) k_explode(const EArgs a) {
+  constexpr int NCH = 1 << L::D;
+  const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int64_t gl = t / NCH;
+  if (gl >= a.count) return;
+  const int64_t gk = a.g0 + gl;
+  const int32_t ch = a.child[gk * NCH + (t % NCH)];
+  if (ch < 0) return;
+  const int64_t G = a.ghost_cell[gk];
+  const S *fin = (const S *)a.fin_coarse;
+  S *fout = (S *)a.fout_fine;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) fout[(int64_t)i * a.stride + ch] = fin[(int64_t)i * a.stride + G];
+  if (DDF) {
+    const S *gin = (const S *)a.gin_coarse;
+    S *gout = (S *)a.gout_fine;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) gout[(int64_t)i * a.stride + ch] = gin[(int64_t)i * a.stride + G];
+  }
+  if (LAM)
+#pragma unroll
+    for (int k = 0; k < NLAM; ++k) a.lam[(int64_t)k * a.stride + ch] = a.lam[(int64_t)k * a.stride + G];
+}
+
+// ---------------------------------------------------------------------------
+// boundary layers: Neumann copy of the source cell's post-collision state;
+// equilibrium Dirichlet with imposed (or extrapolated) density
+// ---------------------------------------------------------------------------
+template <class T6>
+__device__ inline T6 pick6(const T6 (&v)[6], int k) {
+  T6 r = v[0];
+#pragma unroll
+  for (int f = 1; f < 6; ++f)
+    if (f == k) r = v[f];
+  return r;
+}
+
+template <class L, int COLL, class S>
+__global__ void __launch_bounds__(BLOCK) k_bcfill(const BArgs a) {
+  using C = typename Sto<S>::C;
+  constexpr bool DDF = COLL >= COLL_DDF_POLY;
+  constexpr bool LAM = COLL >= COLL_DDF_NEWTON;
+  const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (t >= a.count) return;
+  const int64_t k = a.b0 + t;
+  const int64_t c = a.bc_cell[k], src = a.bc_src[k];
+  const int face = a.bc_face[k];
+  S *f = (S *)a.f;
+  S *g = (S *)a.g;
+  int kind = 0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q)
+    if (q == face) kind = a.fv.extrap[q];
+  const double frho = pick6(a.fv.rho, face), fT = pick6(a.fv.T, face);
+  double fu[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < 6; ++q)
+    if (q == face) { fu[0] = a.fv.u[q][0]; fu[1] = a.fv.u[q][1]; fu[2] = a.fv.u[q][2]; }
+  if (kind < 0) {  // Neumann
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) f[(int64_t)i * a.stride + c] = f[(int64_t)i * a.stride + src];
+    if (DDF)
+#pragma unroll
+      for (int i = 0; i < L::Q; ++i) g[(int64_t)i * a.stride + c] = g[(int64_t)i * a.stride + src];
+    if (LAM)
+#pragma unroll
+      for (int q = 0; q < NLAM; ++q) a.lam[(int64_t)q * a.stride + c] = a.lam[(int64_t)q * a.stride + src];
+    return;
+  }
+  C rho = (C)frho;
+  if (kind == 1) {
+    rho = (C)0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) rho += Sto<S>::ld(f, (int64_t)i * a.stride + src, L::S.w[i]);
+  }
+  C u[3] = {(C)fu[0], (C)fu[1], (C)fu[2]};
+  C feq[L::Q], geq[DDF ? L::Q : 1];
+  double lam[NLAM];
+  if (LAM)
+#pragma unroll
+    for (int q = 0; q < NLAM; ++q) lam[q] = (double)a.lam[(int64_t)q * a.stride + c];
+  const int it = equilibrium_any<L, COLL, C>(rho, u, (C)fT, a.ph, lam, a.ph.warm != 0, feq, geq);
+  if (LAM) {
+    if (it < 0) count_add(a.counters, CNT_NEWTON_FAIL, 1);
+#pragma unroll
+    for (int q = 0; q < NLAM; ++q) a.lam[(int64_t)q * a.stride + c] = (float)lam[q];
+  }
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    Sto<S>::st(f, (int64_t)i * a.stride + c, feq[i], L::S.w[i]);
+    if (DDF) Sto<S>::st(g, (int64_t)i * a.stride + c, geq[i], 0.0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gathers of the synchronisation-point state (pre-collision populations;
+// coarse ghosts read their coalesced slots)
+// ---------------------------------------------------------------------------
+template <class L, class S, bool PRE, bool DDF>
+__global__ void __launch_bounds__(BLOCK) k_gather(const MArgs a) {
+  using C = typename Sto<S>::C;
+  constexpr int Q = L::Q;
+  const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const bool valid = t < a.count;
+  const int64_t c = a.begin + (valid ? t : 0);
+  C f[Q];
+  C g[DDF ? Q : 1];
+  const bool fine_ghost = valid && (a.flags[c] & F_FINE_GHOST);
+  if (valid)
+    gather<L, S, PRE, DDF>((const S *)a.fin, (const S *)a.gin, a.nbr, a.stride, a.vbase, c, a.uw,
+                           a.cs2w, f, g);
+  if (a.mode == 0) {
+    if (!valid) return;
+    const int nm = 1 + L::D + (DDF ? 1 : 0);
+    if (fine_ghost) {
+      for (int k = 0; k < nm; ++k) a.out[(int64_t)k * a.n + c] = __longlong_as_double(0x7ff8000000000000ll);
+      return;
+    }
+    C rho, u[3], T;
+    cell_moments<L, C, DDF>(f, g, (C)a.Cv, rho, u, T);
+    a.out[c] = (double)rho;
+    for (int d = 0; d < L::D; ++d) a.out[(int64_t)(1 + d) * a.n + c] = (double)u[d];
+    if (DDF) a.out[(int64_t)(1 + L::D) * a.n + c] = (double)T;
+    return;
+  }
+  if (a.mode == 1) {
+    if (!valid) return;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      a.out[(int64_t)i * a.n + c] = (double)f[i];
+      if (DDF) a.out[(int64_t)(Q + i) * a.n + c] = (double)g[i];
+    }
+    if (a.lam_out)
+      for (int k = 0; k < NLAM; ++k) a.lam_out[(int64_t)k * a.n + c] = (double)a.lam[(int64_t)k * a.stride + c];
+    return;
+  }
+  // mode 2: volume-weighted conserved sums, deterministic block reduction
+  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (valid && !fine_ghost) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double fi = (double)f[i];
+      s[0] += fi;
+#pragma unroll
+      for (int d = 0; d < L::D; ++d) s[1 + d] += fi * cx_<L>(i, d);
+      const int n2 = cx_<L>(i, 0) * cx_<L>(i, 0) + cx_<L>(i, 1) * cx_<L>(i, 1) + cx_<L>(i, 2) * cx_<L>(i, 2);
+      s[4] += 0.5 * (n2 * fi + (DDF ? (double)g[i] : 0.0));
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) s[k] *= a.vol;
+  }
+  __shared__ double red[BLOCK / 64][6];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double v = s[k];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    s[k] = v;
+  }
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) red[wid][k] = s[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 5; ++k) {
+      double v = 0.0;
+      for (int w = 0; w < BLOCK / 64; ++w) v += red[w][k];
+      a.partials[(int64_t)blockIdx.x * 6 + k] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// initialisation at equilibrium (App. A.3) or restore of raw populations
+// ---------------------------------------------------------------------------
+template <class L, int COLL, class S>
+__global__ void __launch_bounds__(BLOCK) k_init(const IArgs a) {
+  using C = typename Sto<S>::C;
+  constexpr bool DDF = COLL >= COLL_DDF_POLY;
+  constexpr bool LAM = COLL >= COLL_DDF_NEWTON;
+  const int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (c >= a.n) return;
+  S *f = (S *)a.f;
+  S *g = (S *)a.g;
+  if (a.mode == 1) {
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+      Sto<S>::st(f, (int64_t)i * a.stride + c, (C)a.src[(int64_t)i * a.n + c], L::S.w[i]);
+      if (DDF) Sto<S>::st(g, (int64_t)i * a.stride + c, (C)a.src_g[(int64_t)i * a.n + c], 0.0);
+    }
+    if (LAM && a.src_lam)
+      for (int k = 0; k < NLAM; ++k) a.lam[(int64_t)k * a.stride + c] = (float)a.src_lam[(int64_t)k * a.n + c];
+    return;
+  }
+  const C rho = (C)a.src[c];
+  C u[3] = {(C)0, (C)0, (C)0};
+  for (int d = 0; d < L::D; ++d) u[d] = (C)a.src[(int64_t)(1 + d) * a.n + c];
+  const C T = DDF ? (C)a.src[(int64_t)(1 + L::D) * a.n + c] : (C)0;
+  C feq[L::Q], geq[DDF ? L::Q : 1];
+  double lam[NLAM];
+  const int it = equilibrium_any<L, COLL, C>(rho, u, T, a.ph, lam, false, feq, geq);
+  if (LAM) {
+    if (it < 0) count_add(a.counters, CNT_NEWTON_FAIL, 1);
+    for (int k = 0; k < NLAM; ++k) a.lam[(int64_t)k * a.stride + c] = (float)lam[k];
+  }
+  if (!(rho > (C)0) || !isfinite(rho)) count_add(a.counters, CNT_NONFINITE, 1);
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    Sto<S>::st(f, (int64_t)i * a.stride + c, feq[i], L::S.w[i]);
+    if (DDF) Sto<S>::st(g, (int64_t)i * a.stride + c, geq[i], 0.0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+inline unsigned nblocks(int64_t work) { return (unsigned)((work + BLOCK - 1) / BLOCK); }
+
+template <class L, int COLL, class S>
+struct Launch {
+  static constexpr bool DDF = COLL >= COLL_DDF_POLY;
+  static constexpr bool LAM = COLL >= COLL_DDF_NEWTON;
+  static void collide(const KArgs &a, bool pre, hipStream_t s) {
+    if (a.count <= 0) return;
+    if (pre) hipLaunchKernelGGL((k_collide<L, COLL, S, true>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
+    else hipLaunchKernelGGL((k_collide<L, COLL, S, false>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
+  }
+  static void coalesce(const CArgs &a, bool pre, hipStream_t s) {
+    if (a.count <= 0) return;
+    const int64_t work = a.count << L::D;
+    if (pre) hipLaunchKernelGGL((k_coalesce<L, S, true, DDF, LAM>), dim3(nblocks(work)), dim3(BLOCK), 0, s, a);
+    else hipLaunchKernelGGL((k_coalesce<L, S, false, DDF, LAM>), dim3(nblocks(work)), dim3(BLOCK), 0, s, a);
+  }
+  static void explode(const EArgs &a, hipStream_t s) {
+    if (a.count <= 0) return;
+    hipLaunchKernelGGL((k_explode<L, S, DDF, LAM>), dim3(nblocks(a.count << L::D)), dim3(BLOCK), 0, s, a);
+  }
+  static void bcfill(const BArgs &a, hipStream_t s) {
+    if (a.count <= 0) return;
+    hipLaunchKernelGGL((k_bcfill<L, COLL, S>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
+  }
+  static void gather(const MArgs &a, bool pre, hipStream_t s) {
+    if (a.count <= 0) return;
+    if (pre) hipLaunchKernelGGL((k_gather<L, S, true, DDF>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
+    else hipLaunchKernelGGL((k_gather<L, S, false, DDF>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
+  }
+  static void init(const IArgs &a, hipStream_t s) {
+    if (a.n <= 0) return;
+    hipLaunchKernelGGL((k_init<L, COLL, S>), dim3(nblocks(a.n)), dim3(BLOCK), 0, s, a);
+  }
+  static Ops ops() {
+    Ops o;
+    o.collide = &collide;
+    o.coalesce = &coalesce;
+    o.explode = &explode;
+    o.bcfill = &bcfill;
+    o.gather = &gather;
+    o.init = &init;
+    o.sizeof_storage = (int)sizeof(S);
+    return o;
+  }
+};
+
+}  // namespace lbm

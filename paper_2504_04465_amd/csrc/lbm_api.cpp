@@ -1,0 +1,748 @@
+// lbm_api.cpp -- the C-ABI of liblbm.so: context, grid upload, the level
+// scheduler of Sec. 4.5 (asynchronous time stepping, coarsest level first,
+// coupling before collide-and-stream) and the synchronous read-backs.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "grid_builder.h"
+#include "lattice.h"
+#include "lbm.h"
+#include "ops.h"
+
+using namespace lbm;
+
+struct ProfSlot {
+  hipEvent_t a, b;
+  int level;
+};
+
+struct lbm_ctx {
+  lbm_params p{};
+  std::string err;
+  hipStream_t stream = nullptr;
+  lbm_dev_alloc_fn dalloc = nullptr;
+  lbm_dev_free_fn dfree = nullptr;
+  void *actx = nullptr;
+  LatticeInfo lat{};
+  Ops ops{};
+  bool ddf = false, lamf = false;
+  // grid
+  bool have_grid = false;
+  HostGrid g;
+  lbm_face_bc face[6]{};
+  int dim = 0, L = 0;
+  double tau[8]{};
+  int64_t N = 0, Ng = 0, stride = 0;
+  // device
+  std::vector<void *> allocs;
+  void *f[2]{}, *gb[2]{};
+  int32_t *d_nbr = nullptr;
+  uint8_t *d_flags = nullptr;
+  float *d_sigma = nullptr, *d_rhoinf = nullptr, *d_lam = nullptr;
+  int32_t *d_ghost = nullptr, *d_child = nullptr;
+  uint64_t *d_unknown = nullptr;
+  int32_t *d_bc_cell = nullptr, *d_bc_src = nullptr;
+  int8_t *d_bc_face = nullptr;
+  unsigned long long *d_counters = nullptr;
+  double *d_scratch = nullptr;
+  size_t scratch_bytes = 0;
+  int parity[8]{};
+  bool pre[8]{};
+  bool have_state = false;
+  int64_t updates[8]{};
+  int64_t coarse_steps = 0;
+  // profiling
+  bool prof = false;
+  std::vector<ProfSlot> slots;
+  std::vector<hipEvent_t> pool;
+  int64_t prof_launches[8]{};
+  double prof_ms[8]{};
+};
+
+namespace {
+
+lbm_status set_err(lbm_ctx *c, lbm_status s, const std::string &msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                               \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return set_err(ctx, LBM_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+void *dev_alloc(lbm_ctx *c, size_t bytes) {
+  void *p = nullptr;
+  bytes = std::max<size_t>(bytes, 256);
+  if (c->dalloc) {
+    p = c->dalloc(bytes, c->actx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) c->allocs.push_back(p);
+  return p;
+}
+
+void free_device(lbm_ctx *c) {
+  if (c->p.host_only) return;
+  if (!c->allocs.empty()) hipStreamSynchronize(c->stream);
+  for (void *p : c->allocs) {
+    if (c->dfree) c->dfree(p, c->actx);
+    else hipFree(p);
+  }
+  c->allocs.clear();
+  c->f[0] = c->f[1] = c->gb[0] = c->gb[1] = nullptr;
+  c->d_nbr = nullptr;
+  c->d_flags = nullptr;
+  c->d_sigma = c->d_rhoinf = c->d_lam = nullptr;
+  c->d_ghost = c->d_child = nullptr;
+  c->d_unknown = nullptr;
+  c->d_bc_cell = c->d_bc_src = nullptr;
+  c->d_bc_face = nullptr;
+  c->d_counters = nullptr;
+  c->d_scratch = nullptr;
+  c->scratch_bytes = 0;
+}
+
+template <class T>
+lbm_status upload(lbm_ctx *c, T **dst, const T *src, size_t count) {
+  *dst = (T *)dev_alloc(c, count * sizeof(T));
+  if (!*dst) return set_err(c, LBM_E_NOMEM, "device allocation failed");
+  if (count) HIP_TRY(c, hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+  return LBM_OK;
+}
+
+PhysArgs phys(const lbm_ctx *c, int l) {
+  PhysArgs ph{};
+  ph.tau = c->tau[l];
+  ph.cs2w = c->ddf ? c->p.T0 : c->lat.cs2;
+  for (int k = 0; k < 6; ++k)
+    for (int d = 0; d < 3; ++d)
+      ph.uw[k][d] = c->face[k].kind == LBM_BC_MOVING_WALL ? c->face[k].u[d] : 0.0;
+  ph.Cv = 1.0 / (c->p.gamma - 1.0);
+  ph.sensor_A = c->p.sensor_A;
+  ph.sensor_on = c->p.sensor_on;
+  ph.trace_eq = c->p.trace_equilibration;
+  ph.newton_tol = c->p.newton_tol;
+  ph.fallback_tol = c->p.fallback_tol;
+  ph.newton_max_it = c->p.newton_max_it;
+  ph.warm = c->p.lambda_warm_start;
+  ph.mlp = nullptr;
+  return ph;
+}
+
+const void *fbuf(const lbm_ctx *c, int l) { return c->f[c->parity[l]]; }
+const void *gbuf(const lbm_ctx *c, int l) { return c->gb[c->parity[l]]; }
+
+void launch_coalesce(lbm_ctx *c, int l) {
+  const int64_t cnt = c->g.goff[l + 1] - c->g.goff[l];
+  if (cnt <= 0) return;
+  CArgs a{};
+  a.fin_child = fbuf(c, l + 1);
+  a.gin_child = gbuf(c, l + 1);
+  a.fout_coarse = const_cast<void *>(fbuf(c, l));
+  a.gout_coarse = const_cast<void *>(gbuf(c, l));
+  a.lam = c->d_lam;
+  a.stride = c->stride;
+  a.vbase = c->N;
+  a.nbr = c->d_nbr;
+  a.child = c->d_child;
+  a.unknown = c->d_unknown;
+  a.ghost_cell = c->d_ghost;
+  a.g0 = c->g.goff[l];
+  a.count = cnt;
+  PhysArgs ph = phys(c, l);
+  a.cs2w = ph.cs2w;
+  memcpy(a.uw, ph.uw, sizeof a.uw);
+  c->ops.coalesce(a, c->pre[l + 1], c->stream);
+}
+
+void launch_explode(lbm_ctx *c, int l) {
+  const int64_t cnt = c->g.goff[l + 1] - c->g.goff[l];
+  if (cnt <= 0) return;
+  EArgs a{};
+  a.fin_coarse = fbuf(c, l);
+  a.fout_fine = const_cast<void *>(fbuf(c, l + 1));
+  a.gin_coarse = gbuf(c, l);
+  a.gout_fine = const_cast<void *>(gbuf(c, l + 1));
+  a.lam = c->d_lam;
+  a.stride = c->stride;
+  a.child = c->d_child;
+  a.ghost_cell = c->d_ghost;
+  a.g0 = c->g.goff[l];
+  a.count = cnt;
+  c->ops.explode(a, c->stream);
+}
+
+FaceVals face_vals(const lbm_ctx *c) {
+  FaceVals fv{};
+  for (int k = 0; k < 6; ++k) {
+    fv.rho[k] = c->face[k].rho;
+    fv.T[k] = c->face[k].T;
+    for (int d = 0; d < 3; ++d) fv.u[k][d] = c->face[k].u[d];
+    fv.extrap[k] = c->face[k].kind == LBM_BC_EQUILIBRIUM ? (c->face[k].extrapolate_rho ? 1 : 0) : -1;
+  }
+  return fv;
+}
+
+void launch_bcfill(lbm_ctx *c, int l) {
+  const int64_t cnt = c->g.boff[l + 1] - c->g.boff[l];
+  if (cnt <= 0) return;
+  BArgs a{};
+  a.f = const_cast<void *>(fbuf(c, l));
+  a.g = const_cast<void *>(gbuf(c, l));
+  a.lam = c->d_lam;
+  a.stride = c->stride;
+  a.bc_cell = c->d_bc_cell;
+  a.bc_src = c->d_bc_src;
+  a.bc_face = c->d_bc_face;
+  a.b0 = c->g.boff[l];
+  a.count = cnt;
+  a.fv = face_vals(c);
+  a.ph = phys(c, l);
+  a.counters = c->d_counters;
+  c->ops.bcfill(a, c->stream);
+}
+
+hipEvent_t take_event(lbm_ctx *c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  hipEventCreate(&e);
+  return e;
+}
+
+void launch_collide(lbm_ctx *c, int l) {
+  const int64_t cnt = c->g.off[l + 1] - c->g.off[l];
+  if (cnt > 0) {
+    KArgs a{};
+    a.fin = c->f[c->parity[l]];
+    a.fout = c->f[1 - c->parity[l]];
+    a.gin = c->gb[c->parity[l]];
+    a.gout = c->gb[1 - c->parity[l]];
+    a.stride = c->stride;
+    a.vbase = c->N;
+    a.nbr = c->d_nbr;
+    a.flags = c->d_flags;
+    a.sigma = c->d_sigma;
+    a.rho_inf = c->d_rhoinf;
+    a.lam = c->d_lam;
+    a.begin = c->g.off[l];
+    a.count = cnt;
+    a.ph = phys(c, l);
+    a.counters = c->d_counters;
+    ProfSlot slot{};
+    if (c->prof) {
+      slot.a = take_event(c);
+      slot.b = take_event(c);
+      slot.level = l;
+      hipEventRecord(slot.a, c->stream);
+    }
+    c->ops.collide(a, c->pre[l], c->stream);
+    if (c->prof) {
+      hipEventRecord(slot.b, c->stream);
+      c->slots.push_back(slot);
+    }
+    c->updates[l] += cnt;
+  }
+  c->parity[l] ^= 1;
+  c->pre[l] = false;
+}
+
+lbm_status check_launch(lbm_ctx *c) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_err(c, LBM_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return LBM_OK;
+}
+
+lbm_status read_counters(lbm_ctx *c, unsigned long long *out) {
+  HIP_TRY(c, hipMemcpyAsync(out, c->d_counters, CNT_COUNT * sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+lbm_status numeric_check(lbm_ctx *c) {
+  unsigned long long cnt[CNT_COUNT];
+  lbm_status s = read_counters(c, cnt);
+  if (s != LBM_OK) return s;
+  if (cnt[CNT_NEWTON_FAIL] || cnt[CNT_NONFINITE]) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "numerical failure: %llu Newton failures, %llu non-finite cells",
+             cnt[CNT_NEWTON_FAIL], cnt[CNT_NONFINITE]);
+    return set_err(c, LBM_E_NUMERIC, buf);
+  }
+  return LBM_OK;
+}
+
+double *scratch(lbm_ctx *c, size_t bytes) {
+  if (c->scratch_bytes < bytes) {
+    c->d_scratch = (double *)dev_alloc(c, bytes);
+    c->scratch_bytes = c->d_scratch ? bytes : 0;
+  }
+  return c->d_scratch;
+}
+
+// coalesced slots of every coarse ghost, for read-backs of the sync state
+void coalesce_all(lbm_ctx *c) {
+  for (int l = 0; l + 1 < c->L; ++l) launch_coalesce(c, l);
+}
+
+MArgs gather_args(lbm_ctx *c, int l, int mode) {
+  MArgs a{};
+  a.fin = fbuf(c, l);
+  a.gin = gbuf(c, l);
+  a.lam = c->d_lam;
+  a.stride = c->stride;
+  a.vbase = c->N;
+  a.nbr = c->d_nbr;
+  a.flags = c->d_flags;
+  a.begin = c->g.off[l];
+  a.count = c->g.off[l + 1] - c->g.off[l];
+  PhysArgs ph = phys(c, l);
+  a.cs2w = ph.cs2w;
+  memcpy(a.uw, ph.uw, sizeof a.uw);
+  a.Cv = ph.Cv;
+  a.mode = mode;
+  a.n = c->N;
+  a.vol = std::ldexp(1.0, -c->dim * l);
+  return a;
+}
+
+int n_mom(const lbm_ctx *c) { return 1 + c->lat.D + (c->ddf ? 1 : 0); }
+
+lbm_status need_state(lbm_ctx *c) {
+  if (!c) return LBM_E_ARG;
+  if (c->p.host_only) return set_err(c, LBM_E_STATE, "context is host-only");
+  if (!c->have_grid) return set_err(c, LBM_E_STATE, "no grid");
+  if (!c->have_state) return set_err(c, LBM_E_STATE, "not initialised");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_create(const lbm_params *params, lbm_dev_alloc_fn dev_alloc_fn,
+                      lbm_dev_free_fn dev_free_fn, void *alloc_ctx, void *hip_stream,
+                      lbm_ctx **out) {
+  if (!params || !out) return LBM_E_ARG;
+  *out = nullptr;
+  lbm_ctx *c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_E_NOMEM;
+  c->p = *params;
+  c->stream = (hipStream_t)hip_stream;
+  c->dalloc = dev_alloc_fn;
+  c->dfree = dev_free_fn;
+  c->actx = alloc_ctx;
+  const int lat = params->lattice, coll = params->collision, sto = params->storage;
+  if (!get_lattice_info(lat, &c->lat) || coll < 0 || coll > 5 || sto < 0 || sto > 2) {
+    delete c;
+    return LBM_E_ARG;
+  }
+  bool ok = false;
+  switch (lat) {
+    case LBM_D2Q9: ok = get_ops_d2q9(coll, sto, &c->ops); break;
+    case LBM_D3Q27: ok = get_ops_d3q27(coll, sto, &c->ops); break;
+    case LBM_D2Q21: ok = get_ops_d2q21(coll, sto, &c->ops); break;
+    case LBM_D2Q37: ok = get_ops_d2q37(coll, sto, &c->ops); break;
+  }
+  if (!ok) {
+    delete c;
+    return LBM_E_UNSUPPORTED;
+  }
+  if (coll >= LBM_DDF_POLY && !(params->gamma > 1.0)) {
+    delete c;
+    return LBM_E_ARG;
+  }
+  c->ddf = coll >= LBM_DDF_POLY;
+  c->lamf = coll >= LBM_DDF_NEWTON;
+  *out = c;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx *c) {
+  if (!c) return;
+  free_device(c);
+  for (auto &s : c->slots) {
+    hipEventDestroy(s.a);
+    hipEventDestroy(s.b);
+  }
+  for (auto e : c->pool) hipEventDestroy(e);
+  delete c;
+}
+
+const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_levels,
+                          const lbm_mask *refine, const lbm_mask *solid,
+                          const lbm_face_bc faces[6]) {
+  if (!c || !ext || !faces || n_levels < 1 || n_levels > 8) return set_err(c, LBM_E_ARG, "bad arguments");
+  if (n_levels > 1 && !refine) return set_err(c, LBM_E_ARG, "refine masks missing");
+  free_device(c);
+  c->have_grid = false;
+  c->have_state = false;
+  std::vector<MaskView> rv(std::max(1, n_levels - 1)), sv(n_levels);
+  for (int l = 0; l + 1 < n_levels; ++l) {
+    rv[l].data = refine[l].data;
+    for (int a = 0; a < 3; ++a) {
+      rv[l].lo[a] = refine[l].lo[a];
+      rv[l].n[a] = a < dim ? refine[l].n[a] : (refine[l].data ? 1 : 0);
+    }
+  }
+  for (int l = 0; solid && l < n_levels; ++l) {
+    sv[l].data = solid[l].data;
+    for (int a = 0; a < 3; ++a) {
+      sv[l].lo[a] = solid[l].lo[a];
+      sv[l].n[a] = a < dim ? solid[l].n[a] : (solid[l].data ? 1 : 0);
+    }
+  }
+  FaceSpec fs[6];
+  for (int k = 0; k < 6; ++k) {
+    c->face[k] = faces[k];
+    fs[k].kind = faces[k].kind;
+    fs[k].rho = faces[k].rho;
+    for (int d = 0; d < 3; ++d) fs[k].u[d] = faces[k].u[d];
+    fs[k].T = faces[k].T;
+    fs[k].extrapolate_rho = faces[k].extrapolate_rho;
+    fs[k].sponge_sigma_max = faces[k].sponge_sigma_max;
+    fs[k].sponge_width = faces[k].sponge_width;
+  }
+  std::string err;
+  const int rc = build_grid(c->lat, dim, ext, n_levels, rv.data(), solid ? sv.data() : nullptr, fs, &c->g, &err);
+  if (rc != 0) return set_err(c, rc == -2 ? LBM_E_MASK : LBM_E_ARG, err);
+  c->dim = dim;
+  c->L = n_levels;
+  // relaxation time per level, nu_l = nu_finest / 2^(L-1-l) (acoustic scaling)
+  const double cs2e = c->ddf ? c->p.T0 : c->lat.cs2;
+  for (int l = 0; l < n_levels; ++l)
+    c->tau[l] = c->p.nu_finest <= 0.0 ? 0.5 : c->p.nu_finest / std::ldexp(1.0, n_levels - 1 - l) / cs2e + 0.5;
+  c->N = c->g.n;
+  c->Ng = c->g.goff[n_levels];
+  c->stride = ((c->N + c->Ng + 63) / 64) * 64;
+  c->have_grid = true;
+  if (c->p.host_only) return LBM_OK;
+  // ---- device upload ----------------------------------------------------
+  const int Q = c->lat.Q, Qm = Q - 1, NCH = 1 << dim;
+  const size_t ssz = (size_t)c->ops.sizeof_storage;
+  for (int b = 0; b < 2; ++b) {
+    c->f[b] = dev_alloc(c, ssz * Q * c->stride);
+    if (!c->f[b]) return set_err(c, LBM_E_NOMEM, "population allocation failed");
+    if (c->ddf) {
+      c->gb[b] = dev_alloc(c, ssz * Q * c->stride);
+      if (!c->gb[b]) return set_err(c, LBM_E_NOMEM, "population allocation failed");
+    }
+  }
+  // internal neighbour encoding: coalesced slot for unknown coarse-ghost
+  // populations, the cell itself where the own value is kept, -1 for
+  // bounce-back, -2-k for the moving wall of face k
+  std::vector<int32_t> gidx(c->N, -1);
+  for (int64_t k = 0; k < c->Ng; ++k) gidx[c->g.ghost_cell[k]] = (int32_t)k;
+  c->d_nbr = (int32_t *)dev_alloc(c, sizeof(int32_t) * (size_t)Qm * c->stride);
+  if (!c->d_nbr) return set_err(c, LBM_E_NOMEM, "neighbour allocation failed");
+  {
+    std::vector<int32_t> row(c->N);
+    for (int i = 0; i < Qm; ++i) {
+      const int32_t *src = c->g.nbr.data() + (size_t)i * c->N;
+      const int64_t N = c->N;
+#pragma omp parallel for schedule(static)
+      for (int64_t cc = 0; cc < N; ++cc) {
+        const int32_t v = src[cc];
+        int32_t o;
+        if (v >= 0) o = v;
+        else if (v == NBR_NONE) o = gidx[cc] >= 0 ? (int32_t)(N + gidx[cc]) : (int32_t)cc;
+        else if (v == NBR_SOLID) o = -1;
+        else o = -2 - (-3 - v);
+        row[cc] = o;
+      }
+      HIP_TRY(c, hipMemcpy(c->d_nbr + (size_t)i * c->stride, row.data(), sizeof(int32_t) * N,
+                           hipMemcpyHostToDevice));
+    }
+  }
+  lbm_status s;
+  if ((s = upload(c, &c->d_flags, c->g.flag.data(), c->N)) != LBM_OK) return s;
+  if (!c->g.sigma.empty()) {
+    if ((s = upload(c, &c->d_sigma, c->g.sigma.data(), c->N)) != LBM_OK) return s;
+    if ((s = upload(c, &c->d_rhoinf, c->g.rho_inf.data(), c->N)) != LBM_OK) return s;
+  }
+  if (c->lamf) {
+    c->d_lam = (float *)dev_alloc(c, sizeof(float) * NLAM * c->stride);
+    if (!c->d_lam) return set_err(c, LBM_E_NOMEM, "multiplier allocation failed");
+  }
+  if ((s = upload(c, &c->d_ghost, c->g.ghost_cell.data(), c->Ng)) != LBM_OK) return s;
+  if ((s = upload(c, &c->d_child, c->g.child.data(), (size_t)c->Ng * NCH)) != LBM_OK) return s;
+  if ((s = upload(c, &c->d_unknown, c->g.unknown.data(), c->Ng)) != LBM_OK) return s;
+  if ((s = upload(c, &c->d_bc_cell, c->g.bc_cell.data(), c->g.bc_cell.size())) != LBM_OK) return s;
+  if ((s = upload(c, &c->d_bc_src, c->g.bc_src.data(), c->g.bc_src.size())) != LBM_OK) return s;
+  if ((s = upload(c, &c->d_bc_face, c->g.bc_face.data(), c->g.bc_face.size())) != LBM_OK) return s;
+  c->d_counters = (unsigned long long *)dev_alloc(c, sizeof(unsigned long long) * CNT_COUNT);
+  if (!c->d_counters) return set_err(c, LBM_E_NOMEM, "counter allocation failed");
+  HIP_TRY(c, hipMemset(c->d_counters, 0, sizeof(unsigned long long) * CNT_COUNT));
+  return LBM_OK;
+}
+
+lbm_status lbm_grid_info(lbm_ctx *c, int64_t *n_cells, int64_t *n_per_level, int64_t *n_ghosts,
+                         double *eq_fine) {
+  if (!c) return LBM_E_ARG;
+  if (!c->have_grid) return set_err(c, LBM_E_STATE, "no grid");
+  if (n_cells) *n_cells = c->N;
+  if (n_ghosts) *n_ghosts = c->Ng;
+  double e = 0.0;
+  for (int l = 0; l < c->L; ++l) {
+    const int64_t k = c->g.off[l + 1] - c->g.off[l];
+    if (n_per_level) n_per_level[l] = k;
+    e += (double)k / std::ldexp(1.0, c->L - 1 - l);
+  }
+  if (eq_fine) *eq_fine = e;
+  return LBM_OK;
+}
+
+lbm_status lbm_grid_export(lbm_ctx *c, int32_t *coords, int8_t *level, uint8_t *flags, int32_t *nbr,
+                           int32_t *child, int32_t *bc_src) {
+  if (!c) return LBM_E_ARG;
+  if (!c->have_grid) return set_err(c, LBM_E_STATE, "no grid");
+  const int64_t n = c->N;
+  const int Qm = c->lat.Q - 1;
+  if (coords) memcpy(coords, c->g.xyz.data(), sizeof(int32_t) * 3 * n);
+  if (level) memcpy(level, c->g.lev.data(), n);
+  if (flags) memcpy(flags, c->g.flag.data(), n);
+  if (nbr) {
+#pragma omp parallel for schedule(static)
+    for (int64_t cc = 0; cc < n; ++cc)
+      for (int i = 0; i < Qm; ++i) nbr[cc * Qm + i] = c->g.nbr[(size_t)i * n + cc];
+  }
+  if (child) memcpy(child, c->g.child.data(), sizeof(int32_t) * c->g.child.size());
+  if (bc_src) memcpy(bc_src, c->g.bc_src_all.data(), sizeof(int32_t) * n);
+  return LBM_OK;
+}
+
+static lbm_status init_common(lbm_ctx *c, const double *src, const double *src_g, const double *src_lam,
+                              int mode) {
+  if (!c) return LBM_E_ARG;
+  if (c->p.host_only) return set_err(c, LBM_E_STATE, "context is host-only");
+  if (!c->have_grid) return set_err(c, LBM_E_STATE, "no grid");
+  const int64_t n = c->N;
+  const size_t rows = mode == 0 ? (size_t)n_mom(c) : (size_t)c->lat.Q;
+  const size_t need = rows * n + (mode == 1 && c->ddf ? rows * n : 0) + (mode == 1 && src_lam ? NLAM * n : 0);
+  double *d = scratch(c, sizeof(double) * std::max<size_t>(need, 1));
+  if (!d) return set_err(c, LBM_E_NOMEM, "scratch allocation failed");
+  HIP_TRY(c, hipMemcpyAsync(d, src, sizeof(double) * rows * n, hipMemcpyHostToDevice, c->stream));
+  double *dg = nullptr, *dl = nullptr;
+  if (mode == 1 && c->ddf) {
+    dg = d + rows * n;
+    HIP_TRY(c, hipMemcpyAsync(dg, src_g, sizeof(double) * rows * n, hipMemcpyHostToDevice, c->stream));
+  }
+  if (mode == 1 && src_lam && c->lamf) {
+    dl = d + rows * n * (c->ddf ? 2 : 1);
+    HIP_TRY(c, hipMemcpyAsync(dl, src_lam, sizeof(double) * NLAM * n, hipMemcpyHostToDevice, c->stream));
+  }
+  HIP_TRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long) * CNT_COUNT, c->stream));
+  IArgs a{};
+  a.f = c->f[0];
+  a.g = c->gb[0];
+  a.lam = c->d_lam;
+  a.stride = c->stride;
+  a.n = n;
+  a.src = d;
+  a.src_g = dg;
+  a.src_lam = dl;
+  a.mode = mode;
+  a.ph = phys(c, c->L - 1);
+  a.counters = c->d_counters;
+  c->ops.init(a, c->stream);
+  lbm_status s = check_launch(c);
+  if (s != LBM_OK) return s;
+  for (int l = 0; l < c->L; ++l) {
+    c->parity[l] = 0;
+    c->pre[l] = true;
+    c->updates[l] = 0;
+  }
+  c->coarse_steps = 0;
+  c->have_state = true;
+  s = numeric_check(c);
+  if (s != LBM_OK) return s;
+  return LBM_OK;
+}
+
+lbm_status lbm_init(lbm_ctx *c, const double *moments) {
+  if (!moments) return set_err(c, LBM_E_ARG, "null moments");
+  return init_common(c, moments, nullptr, nullptr, 0);
+}
+
+lbm_status lbm_set_state(lbm_ctx *c, const double *f, const double *g, const double *lambda) {
+  if (!f) return set_err(c, LBM_E_ARG, "null populations");
+  if (c && c->ddf && !g) return set_err(c, LBM_E_ARG, "DDF state needs g");
+  return init_common(c, f, g, lambda, 1);
+}
+
+lbm_status lbm_step(lbm_ctx *c, int64_t n) {
+  lbm_status s = need_state(c);
+  if (s != LBM_OK) return s;
+  if (n < 0) return set_err(c, LBM_E_ARG, "negative step count");
+  const int L = c->L;
+  for (int64_t st = 0; st < n; ++st) {
+    for (int t = 0; t < (1 << (L - 1)); ++t) {
+      for (int l = 0; l < L; ++l) {
+        if (t % (1 << (L - 1 - l)) != 0) continue;
+        if (l + 1 < L) launch_coalesce(c, l);
+        launch_collide(c, l);
+        launch_bcfill(c, l);
+        if (l > 0 && t % (1 << (L - l)) == 0) launch_explode(c, l - 1);
+      }
+    }
+    c->coarse_steps++;
+  }
+  return check_launch(c);
+}
+
+lbm_status lbm_set_face_bc(lbm_ctx *c, int face, const lbm_face_bc *bc) {
+  if (!c || !bc || face < 0 || face > 5) return set_err(c, LBM_E_ARG, "bad face");
+  if (c->have_grid && bc->kind != c->face[face].kind) return set_err(c, LBM_E_ARG, "face kind cannot change");
+  c->face[face] = *bc;
+  return LBM_OK;
+}
+
+lbm_status lbm_moments_device(lbm_ctx *c, double *out_dev) {
+  lbm_status s = need_state(c);
+  if (s != LBM_OK) return s;
+  coalesce_all(c);
+  for (int l = 0; l < c->L; ++l) {
+    MArgs a = gather_args(c, l, 0);
+    a.out = out_dev;
+    c->ops.gather(a, c->pre[l], c->stream);
+  }
+  return check_launch(c);
+}
+
+lbm_status lbm_moments(lbm_ctx *c, double *out) {
+  lbm_status s = need_state(c);
+  if (s != LBM_OK) return s;
+  if (!out) return set_err(c, LBM_E_ARG, "null output");
+  const size_t bytes = sizeof(double) * n_mom(c) * c->N;
+  double *d = scratch(c, bytes);
+  if (!d) return set_err(c, LBM_E_NOMEM, "scratch allocation failed");
+  if ((s = lbm_moments_device(c, d)) != LBM_OK) return s;
+  HIP_TRY(c, hipMemcpyAsync(out, d, bytes, hipMemcpyDeviceToHost, c->stream));
+  return numeric_check(c);
+}
+
+lbm_status lbm_get_state(lbm_ctx *c, double *f, double *g, double *lambda) {
+  lbm_status s = need_state(c);
+  if (s != LBM_OK) return s;
+  if (!f || (c->ddf && !g)) return set_err(c, LBM_E_ARG, "null output");
+  const int Q = c->lat.Q;
+  const size_t rows = (size_t)Q * (c->ddf ? 2 : 1);
+  const size_t need = rows * c->N + (c->lamf ? NLAM * c->N : 0);
+  double *d = scratch(c, sizeof(double) * need);
+  if (!d) return set_err(c, LBM_E_NOMEM, "scratch allocation failed");
+  coalesce_all(c);
+  for (int l = 0; l < c->L; ++l) {
+    MArgs a = gather_args(c, l, 1);
+    a.out = d;
+    a.lam_out = c->lamf ? d + rows * c->N : nullptr;
+    c->ops.gather(a, c->pre[l], c->stream);
+  }
+  if ((s = check_launch(c)) != LBM_OK) return s;
+  HIP_TRY(c, hipMemcpyAsync(f, d, sizeof(double) * Q * c->N, hipMemcpyDeviceToHost, c->stream));
+  if (c->ddf)
+    HIP_TRY(c, hipMemcpyAsync(g, d + (size_t)Q * c->N, sizeof(double) * Q * c->N, hipMemcpyDeviceToHost,
+                              c->stream));
+  if (c->lamf && lambda)
+    HIP_TRY(c, hipMemcpyAsync(lambda, d + rows * c->N, sizeof(double) * NLAM * c->N, hipMemcpyDeviceToHost,
+                              c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_stats_get(lbm_ctx *c, lbm_stats *out) {
+  lbm_status s = need_state(c);
+  if (s != LBM_OK) return s;
+  if (!out) return set_err(c, LBM_E_ARG, "null output");
+  memset(out, 0, sizeof *out);
+  std::vector<int64_t> blocks(c->L), boff(c->L + 1, 0);
+  for (int l = 0; l < c->L; ++l) {
+    blocks[l] = (c->g.off[l + 1] - c->g.off[l] + 255) / 256;
+    boff[l + 1] = boff[l] + blocks[l];
+  }
+  double *d = scratch(c, sizeof(double) * 6 * std::max<int64_t>(boff[c->L], 1));
+  if (!d) return set_err(c, LBM_E_NOMEM, "scratch allocation failed");
+  coalesce_all(c);
+  for (int l = 0; l < c->L; ++l) {
+    MArgs a = gather_args(c, l, 2);
+    a.partials = d + 6 * boff[l];
+    c->ops.gather(a, c->pre[l], c->stream);
+  }
+  if ((s = check_launch(c)) != LBM_OK) return s;
+  std::vector<double> h(6 * std::max<int64_t>(boff[c->L], 1));
+  HIP_TRY(c, hipMemcpyAsync(h.data(), d, sizeof(double) * 6 * boff[c->L], hipMemcpyDeviceToHost, c->stream));
+  unsigned long long cnt[CNT_COUNT];
+  if ((s = read_counters(c, cnt)) != LBM_OK) return s;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int64_t b = 0; b < boff[c->L]; ++b)
+    for (int k = 0; k < 5; ++k) acc[k] += h[6 * b + k];
+  out->mass = acc[0];
+  for (int d2 = 0; d2 < 3; ++d2) out->momentum[d2] = acc[1 + d2];
+  out->energy = acc[4];
+  for (int l = 0; l < c->L; ++l) out->updates[l] = c->updates[l];
+  out->newton_calls = (int64_t)cnt[CNT_NEWTON_CALLS];
+  out->newton_iterations = (int64_t)cnt[CNT_NEWTON_ITERS];
+  out->newton_failures = (int64_t)cnt[CNT_NEWTON_FAIL];
+  out->mlp_fallbacks = (int64_t)cnt[CNT_MLP_FALLBACK];
+  out->nonfinite_cells = (int64_t)cnt[CNT_NONFINITE];
+  out->coarse_steps = c->coarse_steps;
+  return LBM_OK;
+}
+
+lbm_status lbm_sync(lbm_ctx *c) {
+  if (!c) return LBM_E_ARG;
+  if (c->p.host_only || !c->have_grid) return LBM_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return numeric_check(c);
+}
+
+lbm_status lbm_profile_enable(lbm_ctx *c, int on) {
+  if (!c) return LBM_E_ARG;
+  c->prof = on != 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_profile_read(lbm_ctx *c, int level, int64_t *launches, double *total_ms,
+                            double *bytes_per_update) {
+  if (!c) return LBM_E_ARG;
+  if (level < 0 || level >= 8) return set_err(c, LBM_E_ARG, "bad level");
+  if (!c->p.host_only && !c->slots.empty()) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (auto &sl : c->slots) {
+      float ms = 0.0f;
+      HIP_TRY(c, hipEventElapsedTime(&ms, sl.a, sl.b));
+      c->prof_ms[sl.level] += ms;
+      c->prof_launches[sl.level] += 1;
+      c->pool.push_back(sl.a);
+      c->pool.push_back(sl.b);
+    }
+    c->slots.clear();
+  }
+  if (launches) *launches = c->prof_launches[level];
+  if (total_ms) *total_ms = c->prof_ms[level];
+  if (bytes_per_update) {
+    const int Q = c->lat.Q;
+    const double s = c->ops.sizeof_storage;
+    double b = 2.0 * Q * s * (c->ddf ? 2 : 1) + 4.0 * (Q - 1);
+    if (c->lamf) b += 2.0 * NLAM * sizeof(float);
+    *bytes_per_update = b;
+  }
+  return LBM_OK;
+}
+
+}  // extern "C"

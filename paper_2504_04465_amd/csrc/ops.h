@@ -1,0 +1,143 @@
+// ops.h -- argument blocks and launcher table shared by the host scheduler
+// and the per-lattice kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace lbm {
+
+enum CollisionKind { COLL_BGK = 0, COLL_RR = 1, COLL_DDF_POLY = 2, COLL_DDF_NEWTON = 3,
+                     COLL_DDF_MLP = 4, COLL_DDF_MLP_NEWTON = 5 };
+enum StorageKind { STO_FP64 = 0, STO_FP32 = 1, STO_FP16 = 2 };
+
+// device counters (unsigned long long)
+enum { CNT_NEWTON_CALLS = 0, CNT_NEWTON_ITERS = 1, CNT_NEWTON_FAIL = 2, CNT_NONFINITE = 3,
+       CNT_MLP_FALLBACK = 4, CNT_COUNT = 8 };
+
+constexpr int NLAM = 8;
+constexpr int MLP_IN = 4, MLP_HID = 64, MLP_OUT = 8;
+
+struct FaceVals {
+  double rho[6], u[6][3], T[6];
+  int extrap[6];
+};
+
+struct PhysArgs {
+  double tau;          // relaxation time of the level
+  double cs2w;         // denominator of the moving-wall term (cs2, or T0 for DDF)
+  double uw[6][3];     // moving-wall velocity per face
+  double Cv, sensor_A; // DDF
+  int sensor_on, trace_eq;
+  double newton_tol, fallback_tol;
+  int newton_max_it, warm;
+  const float *mlp;    // packed MLP parameters (device), or null
+};
+
+// collide-and-stream of the cells [begin, begin + count) of one level
+struct KArgs {
+  const void *fin;
+  void *fout;
+  const void *gin;
+  void *gout;
+  int64_t stride;      // elements between two populations (SoA)
+  int64_t vbase;       // first virtual (coalesced) slot
+  const int32_t *nbr;  // internal pull sources, SoA [Q-1][stride]
+  const uint8_t *flags;
+  const float *sigma, *rho_inf;  // sponge (may be null)
+  float *lam;          // multipliers [8][stride] (DDF_NEWTON family)
+  int64_t begin, count;
+  PhysArgs ph;
+  unsigned long long *counters;
+};
+
+// coalescence of the unknown populations of one level's coarse ghosts
+struct CArgs {
+  const void *fin_child;  // newest buffer of the fine level
+  const void *gin_child;
+  void *fout_coarse;      // newest buffer of the coarse level (virtual slots)
+  void *gout_coarse;
+  float *lam;
+  int64_t stride, vbase;
+  const int32_t *nbr;
+  const int32_t *child;     // [ghost][2^D]
+  const uint64_t *unknown;  // [ghost]
+  const int32_t *ghost_cell;
+  int64_t g0, count;        // ghosts [g0, g0 + count)
+  double cs2w, uw[6][3];
+};
+
+// uniform explosion of coarse-ghost post-collision states into the children
+struct EArgs {
+  const void *fin_coarse;
+  void *fout_fine;
+  const void *gin_coarse;
+  void *gout_fine;
+  float *lam;
+  int64_t stride;
+  const int32_t *child, *ghost_cell;
+  int64_t g0, count;
+};
+
+// boundary-layer fill after the collision of one level
+struct BArgs {
+  void *f;
+  void *g;
+  float *lam;
+  int64_t stride;
+  const int32_t *bc_cell, *bc_src;
+  const int8_t *bc_face;
+  int64_t b0, count;
+  FaceVals fv;
+  PhysArgs ph;
+  unsigned long long *counters;
+};
+
+// gathers of the synchronisation-point state: moments, populations, sums
+struct MArgs {
+  const void *fin;
+  const void *gin;
+  const float *lam;
+  int64_t stride, vbase;
+  const int32_t *nbr;
+  const uint8_t *flags;
+  int64_t begin, count;
+  double cs2w, uw[6][3], Cv;
+  int mode;            // 0: moments, 1: populations (+ multipliers), 2: sums
+  double *out;         // moments [n_mom][n] / populations [Q][n] (g after)
+  double *lam_out;     // [8][n]
+  int64_t n;
+  double vol;          // cell volume 2^(-D l) for sums
+  double *partials;    // [blocks][6]
+};
+
+// initialisation from moments, or restore of a raw state
+struct IArgs {
+  void *f;
+  void *g;
+  float *lam;
+  int64_t stride, n;
+  const double *src;   // moments [n_mom][n] or populations [Q][n]
+  const double *src_g, *src_lam;
+  int mode;            // 0: equilibrium from moments, 1: raw populations
+  PhysArgs ph;
+  unsigned long long *counters;
+};
+
+struct Ops {
+  void (*collide)(const KArgs &, bool pre, hipStream_t);
+  void (*coalesce)(const CArgs &, bool pre_child, hipStream_t);
+  void (*explode)(const EArgs &, hipStream_t);
+  void (*bcfill)(const BArgs &, hipStream_t);
+  void (*gather)(const MArgs &, bool pre, hipStream_t);
+  void (*init)(const IArgs &, hipStream_t);
+  int sizeof_storage;
+};
+
+bool get_ops_d2q9(int coll, int storage, Ops *out);
+bool get_ops_d3q27(int coll, int storage, Ops *out);
+bool get_ops_d2q21(int coll, int storage, Ops *out);
+bool get_ops_d2q37(int coll, int storage, Ops *out);
+
+}  // namespace lbm

@@ -48,6 +48,26 @@ def uniform_noise(seed: int, ids: np.ndarray, stream: int, amplitude: float) -> 
 
 
 @dataclasses.dataclass
+class Mask:
+    """A level mask restricted to a box: `data` (uint8, shape (ny, nx) or
+    (nz, ny, nx)) covers cells [lo, lo + shape) of its level; every cell
+    outside the box is 0."""
+    data: np.ndarray
+    lo: tuple
+
+    @property
+    def n(self):
+        return tuple(reversed(self.data.shape))
+
+    def dense(self, extent) -> np.ndarray:
+        """full array over a level of extent (Ex, Ey[, Ez])."""
+        out = np.zeros(tuple(reversed(tuple(extent))), np.uint8)
+        sl = tuple(slice(self.lo[a], self.lo[a] + self.n[a]) for a in reversed(range(len(extent))))
+        out[sl] = self.data
+        return out
+
+
+@dataclasses.dataclass
 class Face:
     kind: str = "periodic"  # periodic | wall | moving_wall | neumann | equilibrium
     rho: float = 1.0
@@ -66,8 +86,8 @@ class Workload:
     dim: int
     ext: tuple
     n_levels: int
-    refine: List[np.ndarray]
-    solid: List[Optional[np.ndarray]]
+    refine: List[Mask]
+    solid: List[Optional[Mask]]
     faces: List[Face]
     nu_finest: float
     steps: int
@@ -99,27 +119,28 @@ def _level_extent(ext, dim, level):
 
 def _box_mask(ext, dim, level, lo, hi):
     """mask at level `level` of the cells inside the coarse-unit box [lo, hi)."""
-    E = _level_extent(ext, dim, level)
     s = 1 << level
-    axes = []
-    for a in range(dim):
-        x = np.arange(E[a])
-        axes.append((x >= lo[a] * s) & (x < hi[a] * s))
-    if dim == 2:
-        return (axes[1][:, None] & axes[0][None, :]).astype(np.uint8)
-    return (axes[2][:, None, None] & axes[1][None, :, None] & axes[0][None, None, :]).astype(np.uint8)
+    lo_l = tuple(int(lo[a]) * s for a in range(dim))
+    n_l = tuple((int(hi[a]) - int(lo[a])) * s for a in range(dim))
+    return Mask(np.ones(tuple(reversed(n_l)), np.uint8), lo_l)
 
 
-def _centres(ext, dim, level):
-    """coarse-unit coordinates of the cell centres of a level, as a grid."""
+def _body_mask(ext, dim, level, lo, hi, inside):
+    """mask at level `level` of the cells whose centre satisfies `inside`
+    (a function of coarse-unit centre coordinates), searched in the
+    coarse-unit bounding box [lo, hi)."""
+    s = 1 << level
     E = _level_extent(ext, dim, level)
-    s = float(1 << level)
-    g = [(np.arange(E[a]) + 0.5) / s for a in range(dim)]
+    a0 = [max(0, int(math.floor(lo[a] * s)) - 1) for a in range(dim)]
+    a1 = [min(E[a], int(math.ceil(hi[a] * s)) + 1) for a in range(dim)]
+    g = [(np.arange(a0[a], a1[a]) + 0.5) / s for a in range(dim)]
     if dim == 2:
         yy, xx = np.meshgrid(g[1], g[0], indexing="ij")
-        return xx, yy
-    zz, yy, xx = np.meshgrid(g[2], g[1], g[0], indexing="ij")
-    return xx, yy, zz
+        m = inside(xx, yy)
+    else:
+        zz, yy, xx = np.meshgrid(g[2], g[1], g[0], indexing="ij")
+        m = inside(xx, yy, zz)
+    return Mask(m.astype(np.uint8), tuple(a0))
 
 
 def _centre_coords(coords, level):
@@ -164,10 +185,9 @@ def cylinder(scale: int = 1, steps: int = 2000, seed: int = 2, Ma: float = 0.2,
     L = 4
     refine = [_box_mask(ext, dim, l, *boxes[l]) for l in range(L - 1)]
     cx, cy, radius = 256.0 / scale, 256.0 / scale, 20.0 / scale
-    solid = []
-    for l in range(L):
-        xx, yy = _centres(ext, dim, l)
-        solid.append((((xx - cx) ** 2 + (yy - cy) ** 2) <= radius * radius).astype(np.uint8))
+    solid = [_body_mask(ext, dim, l, (cx - radius, cy - radius), (cx + radius, cy + radius),
+                        lambda xx, yy: (xx - cx) ** 2 + (yy - cy) ** 2 <= radius * radius)
+             for l in range(L)]
     uinf = Ma * math.sqrt(1.0 / 3.0)
     d_fine = 2 * radius * (1 << (L - 1))
     nu_f = uinf * d_fine / Re
@@ -198,10 +218,9 @@ def sphere(scale: int = 1, steps: int = 500, seed: int = 3, Ma: float = 0.1,
     L = 3
     refine = [_box_mask(ext, dim, l, *boxes[l]) for l in range(L - 1)]
     c0, radius = 128.0 / scale, 16.0 / scale
-    solid = []
-    for l in range(L):
-        xx, yy, zz = _centres(ext, dim, l)
-        solid.append((((xx - c0) ** 2 + (yy - c0) ** 2 + (zz - c0) ** 2) <= radius * radius).astype(np.uint8))
+    solid = [_body_mask(ext, dim, l, (c0 - radius,) * 3, (c0 + radius,) * 3,
+                        lambda xx, yy, zz: (xx - c0) ** 2 + (yy - c0) ** 2 + (zz - c0) ** 2 <= radius * radius)
+             for l in range(L)]
     uinf = Ma * math.sqrt(1.0 / 3.0)
     nu_f = uinf * 2 * radius * (1 << (L - 1)) / Re
     nm = Face("neumann", rho=1.0)
@@ -267,12 +286,12 @@ def airfoil(scale: int = 1, steps: int = 1000, Ma: float = 1.5, Ma0: float = 1.0
     L = 3
     refine = [_box_mask(ext, dim, l, *boxes[l]) for l in range(L - 1)]
     chord, le_x, le_y = 64.0 / scale, 704.0 / scale, 512.0 / scale
-    solid = []
-    for l in range(L):
-        xx, yy = _centres(ext, dim, l)
+    def inside(xx, yy):
         xi = (xx - le_x) / chord
-        inside = (xi >= 0.0) & (xi <= 1.0) & (np.abs(yy - le_y) / chord <= naca_half_thickness(xi))
-        solid.append(inside.astype(np.uint8))
+        return (xi >= 0.0) & (xi <= 1.0) & (np.abs(yy - le_y) / chord <= naca_half_thickness(xi))
+
+    solid = [_body_mask(ext, dim, l, (le_x, le_y - 0.1 * chord), (le_x + chord, le_y + 0.1 * chord), inside)
+             for l in range(L)]
     gamma = 1.4
     cs = math.sqrt(gamma * T0)
     uinf = Ma * cs

@@ -1,0 +1,63 @@
+"""Helpers shared by the GPU parity tests: run a workload on the HIP library
+and on the oracle from the same seeded inputs, and compare the macroscopic
+fields with the volume-weighted relative L2 norm."""
+import sys
+
+import numpy as np
+
+from oracle.oracle import Oracle
+from paper_2504_04465_amd import lbm as B
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(q, ref, vol):
+    ok = ~np.isnan(ref)
+    num = np.sqrt(np.sum(vol[ok] * (q[ok] - ref[ok]) ** 2))
+    den = np.sqrt(np.sum(vol[ok] * ref[ok] ** 2))
+    return float(num / den) if den > 0 else float(num)
+
+
+def compare(m_gpu, m_ref, level, dim):
+    """relative L2 of rho, of rho - mean(rho), of the velocity vector and
+    (DDF) of T; volumes 2^(-D l)."""
+    vol = 0.5 ** (dim * level.astype(np.float64))
+    ok = ~np.isnan(m_ref[0])
+    assert np.array_equal(np.isnan(m_gpu[0]), ~ok), "fine-ghost NaN pattern differs"
+    out = {"rho": rel_l2(m_gpu[0], m_ref[0], vol)}
+    rbar = np.sum(vol[ok] * m_ref[0][ok]) / np.sum(vol[ok])
+    out["drho"] = rel_l2(m_gpu[0] - rbar, m_ref[0] - rbar, vol)
+    du = np.concatenate([m_gpu[1 + d][ok] - m_ref[1 + d][ok] for d in range(dim)])
+    uu = np.concatenate([m_ref[1 + d][ok] for d in range(dim)])
+    vv = np.concatenate([vol[ok]] * dim)
+    out["u"] = float(np.sqrt(np.sum(vv * du ** 2)) / max(np.sqrt(np.sum(vv * uu ** 2)), 1e-300))
+    if m_ref.shape[0] > 1 + dim:
+        out["T"] = rel_l2(m_gpu[1 + dim], m_ref[1 + dim], vol)
+    return out
+
+
+def run_pair(w, steps, storage, oracle_over=None, lib_over=None, schedule=True):
+    """same workload, same seeded initial moments, `steps` coarse steps on
+    both sides; returns (gpu moments, oracle moments, levels, gpu handle)."""
+    o = Oracle.from_workload(w, **(oracle_over or {}))
+    s = B.LBM.from_workload(w, storage=storage, **(lib_over or {}))
+    e = o.export()
+    coords, level = s.coords_levels()
+    assert np.array_equal(coords, e["coords"]) and np.array_equal(level, e["level"])
+    m0 = w.initial_moments(coords, level)
+    o.init(m0)
+    s.init(m0)
+    if not (schedule and w.schedule is not None):
+        o.step(steps)
+        s.step(steps)
+    else:
+        for k in range(steps):
+            for face, f in w.schedule(k).items():
+                o.set_face(face, f)
+                s.set_face(face, f)
+            o.step(1)
+            s.step(1)
+    return s.moments(), o.moments(), level, s, o

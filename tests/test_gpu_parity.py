@@ -1,0 +1,108 @@
+"""GPU parity: the HIP library (through the C-ABI) against the FP64 oracle on
+the same seeded inputs.  FP64 storage must agree to relative L2 <= 1e-12 on
+density and velocity; reduced-precision storage reports its relative L2 and
+must stay within the bound derived for its arithmetic."""
+import numpy as np
+import pytest
+
+from gpu_util import compare, run_pair, say
+from paper_2504_04465_amd import lbm as B
+from paper_2504_04465_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+
+
+def check(name, w, steps, storage, tol_u, tol_rho=None, **kw):
+    say(f"[parity] {name} storage={storage} steps={steps}")
+    mg, mo, level, s, o = run_pair(w, steps, storage, **kw)
+    err = compare(mg, mo, level, w.dim)
+    say(f"[parity] {name} {storage}: {err}")
+    assert err["u"] <= tol_u, err
+    assert err["rho"] <= (tol_rho if tol_rho is not None else tol_u), err
+    return err, s, o
+
+
+def test_cavity_fp64_1000_steps():
+    """Two-level lid-driven cavity, D2Q9 BGK FP64, 1000 coarse steps: the
+    refinement interface meets both side walls."""
+    w = W.cavity(n=64, steps=1000)
+    err, s, o = check("cavity64", w, 1000, "fp64", FP64_TOL)
+    st = s.stats()
+    assert st["updates"] == [1000 * 1 * int(s.n_per_level[0]), 1000 * 2 * int(s.n_per_level[1])]
+
+
+def test_shear_refined_periodic_fp64_conserves():
+    w = W.shear(n=32, levels=3, kind="random", u0=0.03, nu_finest=0.02,
+                band=[(0.25, 0.75), (0.375, 0.625)])
+    err, s, o = check("shear3", w, 40, "fp64", FP64_TOL)
+    st = s.stats()
+    ref = o.sums()
+    assert abs(st["mass"] - ref[0]) < 1e-12 * abs(ref[0])
+    s0 = B.LBM.from_workload(w)
+    s0.init_workload(w)
+    m0 = s0.stats()["mass"]
+    assert abs(st["mass"] - m0) < 2e-13 * abs(m0)
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", FP64_TOL), ("fp32", 2e-5)])
+def test_cylinder_rr(storage, tol):
+    """four-level cylinder (1/8 scale), D2Q9 RR, Ladd inflow, Neumann faces
+    with the pressure sponge"""
+    w = W.cylinder(scale=8, steps=40)
+    check("cylinder/8", w, 40, storage, tol)
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", FP64_TOL), ("fp32", 1e-4), ("fp16", 3e-2)])
+def test_sphere_rr(storage, tol):
+    """three-level sphere (1/8 scale), D3Q27 RR"""
+    w = W.sphere(scale=8, steps=10)
+    check("sphere/8", w, 10, storage, tol)
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", FP64_TOL), ("fp32", 1e-4)])
+def test_sod_d2q37(storage, tol):
+    """D2Q37 DDF shock tube with a refined band and the kinetic sensor"""
+    w = W.sod(nx=256, ny=8)
+    check("sod256", w, w.steps, storage, tol, tol_rho=tol)
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+def test_airfoil_d2q21_newton(storage, tol):
+    """D2Q21 numerical equilibrium (Newton), three levels, equilibrium
+    Dirichlet faces with the Mach ramp, kinetic sensor (1/16 scale)"""
+    w = W.airfoil(scale=16, steps=20)
+    err, s, o = check("airfoil/16", w, 20, storage, tol)
+    st = s.stats()
+    assert st["newton_failures"] == 0 and st["newton_calls"] > 0
+
+
+def test_restart_is_bit_exact():
+    w = W.cylinder(scale=16, steps=10)
+    a = B.LBM.from_workload(w, storage="fp64")
+    a.init_workload(w)
+    a.step(10)
+    ma = a.moments()
+    b = B.LBM.from_workload(w, storage="fp64")
+    b.init_workload(w)
+    b.step(4)
+    f, g, lam = b.get_state()
+    c = B.LBM.from_workload(w, storage="fp64")
+    c.set_state(f, g, lam)
+    c.step(6)
+    assert np.array_equal(np.isnan(ma), np.isnan(c.moments()))
+    mc = c.moments()
+    ok = ~np.isnan(ma)
+    assert np.array_equal(ma[ok], mc[ok])
+
+
+def test_numeric_failure_is_latched():
+    w = W.cavity(n=16, steps=1)
+    s = B.LBM.from_workload(w)
+    m = np.zeros((3, s.n))
+    m[0] = 1.0
+    m[0, 5] = np.nan
+    with pytest.raises(B.LbmError) as e:
+        s.init(m)
+    assert e.value.code == -6

@@ -26,15 +26,14 @@ def tiny_cases():
     cases.append(("cyl", W.cylinder(scale=32, steps=1)))
     cases.append(("sod", W.sod(nx=64, ny=8, steps=1)))
     w3 = W.shear(n=8, levels=2, lattice="D3Q27", collision="RR", steps=1)
-    box = np.zeros((8, 8, 8), np.uint8)
-    box[3:6, 3:6, 3:6] = 1
-    w3.refine = [box]
+    w3.refine = [W.Mask(np.ones((3, 3, 3), np.uint8), (3, 3, 3))]
     sol = []
     for l in range(2):
         e = 8 << l
         g = (np.arange(e) + 0.5) / (1 << l)
         zz, yy, xx = np.meshgrid(g, g, g, indexing="ij")
-        sol.append((((xx - 1.5) ** 2 + (yy - 5.0) ** 2 + (zz - 5.0) ** 2) <= 1.0).astype(np.uint8))
+        sol.append(W.Mask((((xx - 1.5) ** 2 + (yy - 5.0) ** 2 + (zz - 5.0) ** 2) <= 1.0).astype(np.uint8),
+                          (0, 0, 0)))
     w3.solid = sol
     w3.faces = [W.Face("moving_wall", u=(0.05, 0, 0)), W.Face("neumann"), W.Face("wall"), W.Face("wall"),
                 W.Face("periodic"), W.Face("periodic")]
@@ -44,7 +43,7 @@ def tiny_cases():
     m = np.zeros((24, 24), np.uint8)
     m[6:18, 4:20] = 1
     m[10:14, 2:4] = 1
-    w.refine = [m]
+    w.refine = [W.Mask(m, (0, 0))]
     w.faces = [W.Face("wall"), W.Face("wall"), W.Face("periodic"), W.Face("periodic"), W.Face(), W.Face()]
     cases.append(("blob", w))
     return cases
@@ -79,7 +78,7 @@ def test_grid_brute_force(name, w):
     any_solid = np.zeros_like(cover, dtype=bool)
     for l in range(L):
         if w.solid[l] is not None:
-            up = w.solid[l].astype(bool)
+            up = w.solid[l].dense(E[l]).astype(bool)
             for ax in range(D):
                 up = np.repeat(up, 1 << (fine - l), axis=ax)
             any_solid |= up
@@ -129,7 +128,7 @@ def test_grid_brute_force(name, w):
             else:
                 assert got in (NONE, SOLID)
                 if got == SOLID:
-                    assert w.solid[l] is not None and w.solid[l][tuple(reversed(src))] == 1
+                    assert w.solid[l] is not None and w.solid[l].dense(E[l])[tuple(reversed(src))] == 1
     # bulk cells pull every population from a cell; neighbour links are
     # mutual between cells whose populations stream both ways
     for c in range(n):
@@ -148,7 +147,7 @@ def test_coarse_ghost_unknowns_lie_inside_refined_region():
     w = W.shear(n=16, levels=2, steps=1)
     o = Oracle.from_workload(w)
     e = o.export()
-    ref = w.refine[0]
+    ref = w.refine[0].dense((16, 16))
     for c in np.nonzero(e["flags"] & F_COARSE_GHOST)[0]:
         x, y = e["coords"][c][:2]
         for i in range(1, o.Q):
@@ -162,9 +161,9 @@ def test_mask_validation():
     with pytest.raises(RuntimeError, match="too close"):
         Oracle.from_workload(w)
     w = W.shear(n=16, levels=3, steps=1)
-    r1 = np.zeros_like(w.refine[1])
+    r1 = np.zeros((32, 32), np.uint8)
     r1[0:4, :] = 1  # level-1 refinement outside the level-1 region
-    w.refine[1] = r1
+    w.refine[1] = W.Mask(r1, (0, 0))
     with pytest.raises(RuntimeError, match="nested"):
         Oracle.from_workload(w)
 
