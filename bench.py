@@ -92,7 +92,7 @@ def main():
     ap.add_argument("--storage", default=None)
     ap.add_argument("--scale", type=int, default=1)
     ap.add_argument("--cpu-scale", type=int, default=4)
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-child", action="store_true")
     args = ap.parse_args()

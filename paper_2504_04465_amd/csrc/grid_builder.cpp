@@ -396,8 +396,8 @@ int build_grid(const LatticeInfo &lat, int dim, const int32_t ext_in[3], int L,
     if (faces[fc].kind != BC_PERIODIC && faces[fc].sponge_sigma_max > 0.0 && faces[fc].sponge_width > 0.0)
       any_sponge = true;
   if (any_sponge) {
-    g.sigma.assign(n, 0.0f);
-    g.rho_inf.assign(n, 1.0f);
+    g.sigma.assign(n, 0.0);
+    g.rho_inf.assign(n, 1.0);
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < n; ++c) {
       const int l = g.lev[c];
@@ -412,8 +412,8 @@ int build_grid(const LatticeInfo &lat, int dim, const int32_t ext_in[3], int L,
         const double s = F.sponge_sigma_max * ramp;
         if (s > best) { best = s; rinf = F.rho; }
       }
-      g.sigma[c] = (float)best;
-      g.rho_inf[c] = (float)rinf;
+      g.sigma[c] = best;
+      g.rho_inf[c] = rinf;
       if (best > 0.0) g.flag[c] |= F_SPONGE;
     }
   }

@@ -60,8 +60,8 @@ struct HostGrid {
   std::vector<int8_t> bc_face;       // face whose values apply
   int64_t boff[9] = {0};             // boundary cells of level l
   std::vector<int32_t> bc_src_all;   // [n], -1 for cells outside boundary layers
-  std::vector<float> sigma;          // [n] sponge strength (empty if none)
-  std::vector<float> rho_inf;        // [n] sponge target density
+  std::vector<double> sigma;         // [n] sponge strength (empty if none)
+  std::vector<double> rho_inf;       // [n] sponge target density
 };
 
 // Returns 0, -1 (argument error) or -2 (mask error); *err receives the text.

@@ -44,7 +44,8 @@ struct lbm_ctx {
   void *f[2]{}, *gb[2]{};
   int32_t *d_nbr = nullptr;
   uint8_t *d_flags = nullptr;
-  float *d_sigma = nullptr, *d_rhoinf = nullptr, *d_lam = nullptr;
+  double *d_sigma = nullptr, *d_rhoinf = nullptr;
+  float *d_lam = nullptr;
   int32_t *d_ghost = nullptr, *d_child = nullptr;
   uint64_t *d_unknown = nullptr;
   int32_t *d_bc_cell = nullptr, *d_bc_src = nullptr;
@@ -102,7 +103,8 @@ void free_device(lbm_ctx *c) {
   c->f[0] = c->f[1] = c->gb[0] = c->gb[1] = nullptr;
   c->d_nbr = nullptr;
   c->d_flags = nullptr;
-  c->d_sigma = c->d_rhoinf = c->d_lam = nullptr;
+  c->d_sigma = c->d_rhoinf = nullptr;
+  c->d_lam = nullptr;
   c->d_ghost = c->d_child = nullptr;
   c->d_unknown = nullptr;
   c->d_bc_cell = c->d_bc_src = nullptr;

@@ -45,7 +45,7 @@ struct KArgs {
   int64_t vbase;       // first virtual (coalesced) slot
   const int32_t *nbr;  // internal pull sources, SoA [Q-1][stride]
   const uint8_t *flags;
-  const float *sigma, *rho_inf;  // sponge (may be null)
+  const double *sigma, *rho_inf; // sponge (may be null)
   float *lam;          // multipliers [8][stride] (DDF_NEWTON family)
   int64_t begin, count;
   PhysArgs ph;
