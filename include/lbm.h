@@ -217,6 +217,46 @@ lbm_status lbm_get_state(lbm_ctx *ctx, double *f, double *g, double *lambda);
 lbm_status lbm_set_state(lbm_ctx *ctx, const double *f, const double *g,
                          const double *lambda);
 
+/* ---- multiplier surrogate (D2Q21 contexts) ----------------------------
+ * A small network replaces the per-cell Newton solve of the numerical
+ * equilibrium (App. A.2, Eq. exponential, constraints G(0)..G(3)): it maps
+ * (rho, u_x, u_y, T) to the eight multipliers.  Network 4 -> 64 -> 64 -> 64
+ * -> 8, SiLU hidden layers, evaluated and trained on BF16 matrix cores with
+ * FP32 accumulation and FP32 master weights (Adam).  Packed parameters, 9176
+ * floats: W1[64][4] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[8][64]
+ * b4[8] mu[8] sigma[8]; inputs are normalised as ((rho-2.6)/2.4, u_x/2.5,
+ * u_y/2.5, (T-1.75)/1.25), outputs as lambda = mu + sigma * y.  Host arrays
+ * are row-major per sample.  LBM_E_ARG when the context is not D2Q21, or a
+ * size is not a multiple of 32 where one is required. */
+enum { LBM_MLP_PARAMS = 9176 };
+
+lbm_status lbm_mlp_set_weights(lbm_ctx *ctx, const float *w, int64_t n);
+lbm_status lbm_mlp_get_weights(lbm_ctx *ctx, float *w, int64_t n);
+
+/* Newton labels (FP64, cold start lambda = 0, the context's newton_tol and
+ * newton_max_it): x [n][4] = (rho, u_x, u_y, T) -> lambda [n][8];
+ * ok[i] = 1 when converged (unrealisable moments do not converge);
+ * iterations[i] = Newton iterations (-1 when not converged). */
+lbm_status lbm_mlp_label(lbm_ctx *ctx, const double *x, int64_t n, double *lambda, uint8_t *ok,
+                         int32_t *iterations);
+
+/* Surrogate prediction: x [n][4] -> lambda [n][8]. */
+lbm_status lbm_mlp_predict(lbm_ctx *ctx, const double *x, int64_t n, double *lambda);
+
+/* Loss (mean Huber loss, delta 0.5, on normalised outputs) and its gradient with
+ * respect to the packed parameters (9160 trainable entries) for one batch of
+ * normalised inputs xh [n][4] and targets th [n][8]; n a multiple of 32. */
+lbm_status lbm_mlp_grad(lbm_ctx *ctx, const float *xh, const float *th, int64_t n, double *loss,
+                        float *grad);
+
+/* Train on samples x [n][4] with Newton labels lambda [n][8]: mu / sigma are
+ * taken from the labels, weights start from the ones set (or a seeded
+ * initialisation), `epochs` passes in seeded random order, mini-batches of
+ * `batch` (multiple of 32), Adam with a cosine-decayed learning rate.
+ * epoch_loss [epochs] receives the mean training loss of every pass. */
+lbm_status lbm_mlp_train(lbm_ctx *ctx, const double *x, const double *lambda, int64_t n, int epochs,
+                         int batch, double lr, uint64_t seed, double *epoch_loss);
+
 const char *lbm_last_error(const lbm_ctx *ctx);
 void lbm_destroy(lbm_ctx *ctx);
 

@@ -401,10 +401,11 @@ static double norm2(const double *G) {
   return sqrt(acc);
 }
 
+/* largest |G_a|; a NaN residual propagates, so it never passes the tolerance */
 static double normmax(const double *G) {
   double mx = 0.0;
   for (int a = 0; a < NLAM; ++a)
-    if (fabs(G[a]) > mx) mx = fabs(G[a]);
+    if (!(fabs(G[a]) <= mx)) mx = fabs(G[a]);
   return mx;
 }
 

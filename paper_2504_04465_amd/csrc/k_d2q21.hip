@@ -1,14 +1,128 @@
 // Kernel instantiations for D2Q21: double distribution with the numerical
-// (entropy-maximising) equilibrium solved by Newton, FP64 / FP32 storage.
+// (entropy-maximising) equilibrium solved by Newton, or predicted by the
+// multiplier surrogate (alone, or with one Newton correction and a Newton
+// fallback); FP64 / FP32 storage.
 #include "kernels.cuh"
+#include "mlp.cuh"
 
 namespace lbm {
 using L21 = Lattice<LAT_D2Q21>;
 
+// Collide-and-stream with the surrogate: every wavefront evaluates the MLP
+// for its 64 cells (two 32-cell tiles on the matrix cores), then each cell
+// takes the predicted multipliers (DDF_MLP), or one Newton correction from
+// them with a full Newton fallback above fallback_tol (DDF_MLP_NEWTON).
+template <int COLL, class S, bool PRE>
+__global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
+  using L = L21;
+  using C = typename Sto<S>::C;
+  constexpr int Q = L::Q;
+  __shared__ __align__(16) __bf16 xin[BLOCK / 64][2][32 * 16];
+  __shared__ __align__(16) __bf16 ha[BLOCK / 64][32 * 64];
+  __shared__ __align__(16) __bf16 hb[BLOCK / 64][32 * 64];
+  __shared__ float yb[BLOCK / 64][2][32 * 8];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t t = xcd_block() * BLOCK + threadIdx.x;
+  const bool valid = t < a.count;
+  const int64_t c = a.begin + (valid ? t : 0);
+  const int64_t stride = a.stride;
+  C f[Q], g[Q];
+  uint8_t fl = 0;
+  C rho = (C)1, u[3] = {(C)0, (C)0, (C)0}, T = (C)1;
+  if (valid) {
+    fl = a.flags[c];
+    gather<L, S, PRE, true>((const S *)a.fin, (const S *)a.gin, a.nbr, stride, a.vbase, c, a.ph.uw, a.ph.cs2w,
+                            f, g);
+    cell_moments<L, C, true>(f, g, (C)a.ph.Cv, rho, u, T);
+  }
+  const bool collide = valid && !(fl & (F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ));
+  // the multipliers depend on (u, T) only; non-colliding lanes feed a benign state
+  mlp_input_row(&xin[w][l >> 5][(l & 31) * 16], collide ? (float)rho : 1.0f, collide ? (float)u[0] : 0.0f,
+                collide ? (float)u[1] : 0.0f, collide ? (float)T : 1.0f);
+  __syncthreads();
+  const MlpOperands *P = (const MlpOperands *)a.ph.mlp;
+#pragma unroll
+  for (int tile = 0; tile < 2; ++tile) mlp_forward_tile(P, xin[w][tile], ha[w], hb[w], ha[w], yb[w][tile], nullptr);
+  if (collide) {
+    double lam[NLAM];
+#pragma unroll
+    for (int k = 0; k < NLAM; ++k) lam[k] = (double)P->mu[k] + (double)P->sig[k] * (double)yb[w][l >> 5][(l & 31) * 8 + k];
+    C rhop = rho;
+    if (fl & F_SPONGE) {
+      const C s = (C)a.sigma[c];
+      rhop = rho * ((C)1 - s) + s * (C)a.rho_inf[c];
+    }
+    if (!(rho > (C)0) || !isfinite(rho)) count_add(a.counters, CNT_NONFINITE, 1);
+    double e[Q], M[NLAM], G[NLAM];
+    targets<L>((double)u[0], (double)u[1], (double)T, M);
+    expo_residual<L>(lam, M, e, G);
+    if constexpr (COLL == COLL_DDF_MLP_NEWTON) {
+      const bool ok = newton_step<L>(lam, G, e, M);
+      if (!ok || !(nrmmax_8(G) <= a.ph.fallback_tol)) {
+        count_add(a.counters, CNT_MLP_FALLBACK, 1);
+        count_add(a.counters, CNT_NEWTON_CALLS, 1);
+        const int it = newton_solve<L>((double)u[0], (double)u[1], (double)T, lam, a.ph.newton_tol,
+                                       a.ph.newton_max_it, e);
+        if (it < 0) count_add(a.counters, CNT_NEWTON_FAIL, 1);
+        else count_add(a.counters, CNT_NEWTON_ITERS, (unsigned long long)it);
+      }
+    }
+    C feq[Q], geq[Q];
+    const C kg = ((C)2 * (C)a.ph.Cv - (C)L::D) * T;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      feq[i] = (C)((double)rhop * e[i]);
+      geq[i] = kg * feq[i];
+    }
+    C te = (C)a.ph.tau;
+    if (a.ph.sensor_on) te *= sensor_alpha<L, C>(f, feq, te, (C)a.ph.sensor_A);
+    const C om = (C)1 / te;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      f[i] = f[i] - om * (f[i] - feq[i]);
+      g[i] = g[i] - om * (g[i] - geq[i]);
+    }
+  }
+  if (valid) {
+    S *fout = (S *)a.fout;
+    S *gout = (S *)a.gout;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      Sto<S>::st(fout, (int64_t)i * stride + c, f[i], L::S.w[i]);
+      Sto<S>::st(gout, (int64_t)i * stride + c, g[i], 0.0);
+    }
+  }
+}
+
+template <int COLL, class S>
+struct LaunchMlp {
+  static void collide(const KArgs &a, bool pre, hipStream_t s) {
+    if (a.count <= 0) return;
+    if (pre) hipLaunchKernelGGL((k_collide_mlp<COLL, S, true>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
+    else hipLaunchKernelGGL((k_collide_mlp<COLL, S, false>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
+  }
+  static Ops ops() {
+    Ops o = Launch<L21, COLL_DDF_NEWTON, S>::ops();
+    o.collide = &collide;
+    return o;
+  }
+};
+
 bool get_ops_d2q21(int coll, int storage, Ops *out) {
-  if (coll != COLL_DDF_NEWTON) return false;
-  if (storage == STO_FP64) { *out = Launch<L21, COLL_DDF_NEWTON, double>::ops(); return true; }
-  if (storage == STO_FP32) { *out = Launch<L21, COLL_DDF_NEWTON, float>::ops(); return true; }
-  return false;
+  if (storage != STO_FP64 && storage != STO_FP32) return false;
+  const bool f64 = storage == STO_FP64;
+  switch (coll) {
+    case COLL_DDF_NEWTON:
+      *out = f64 ? Launch<L21, COLL_DDF_NEWTON, double>::ops() : Launch<L21, COLL_DDF_NEWTON, float>::ops();
+      return true;
+    case COLL_DDF_MLP:
+      *out = f64 ? LaunchMlp<COLL_DDF_MLP, double>::ops() : LaunchMlp<COLL_DDF_MLP, float>::ops();
+      return true;
+    case COLL_DDF_MLP_NEWTON:
+      *out = f64 ? LaunchMlp<COLL_DDF_MLP_NEWTON, double>::ops() : LaunchMlp<COLL_DDF_MLP_NEWTON, float>::ops();
+      return true;
+    default:
+      return false;
+  }
 }
 }  // namespace lbm

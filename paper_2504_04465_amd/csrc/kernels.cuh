@@ -366,10 +366,14 @@ __device__ inline double nrm2_8(const double *G) {
   return s;
 }
 
+// largest |G_a|; a NaN propagates so that it never passes a tolerance test
 __device__ inline double nrmmax_8(const double *G) {
   double s = 0.0;
 #pragma unroll
-  for (int a = 0; a < NLAM; ++a) s = fmax(s, fabs(G[a]));
+  for (int a = 0; a < NLAM; ++a) {
+    const double v = fabs(G[a]);
+    s = (v > s || v != v) ? v : s;
+  }
   return s;
 }
 

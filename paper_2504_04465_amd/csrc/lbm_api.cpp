@@ -13,7 +13,10 @@
 #include "grid_builder.h"
 #include "lattice.h"
 #include "lbm.h"
+#include "mlp_ops.h"
 #include "ops.h"
+
+#include <random>
 
 using namespace lbm;
 
@@ -58,6 +61,11 @@ struct lbm_ctx {
   bool have_state = false;
   int64_t updates[8]{};
   int64_t coarse_steps = 0;
+  // multiplier surrogate
+  float *d_mlp_w = nullptr, *d_mlp_m = nullptr, *d_mlp_v = nullptr, *d_mlp_g = nullptr;
+  void *d_mlp_ops = nullptr;
+  float *d_mlp_loss = nullptr;
+  bool have_mlp = false;
   // profiling
   bool prof = false;
   std::vector<ProfSlot> slots;
@@ -112,6 +120,21 @@ void free_device(lbm_ctx *c) {
   c->d_counters = nullptr;
   c->d_scratch = nullptr;
   c->scratch_bytes = 0;
+  c->d_mlp_w = c->d_mlp_m = c->d_mlp_v = c->d_mlp_g = c->d_mlp_loss = nullptr;
+  c->d_mlp_ops = nullptr;
+  c->have_mlp = false;
+}
+
+void dev_release(lbm_ctx *c, void *p) {
+  if (!p) return;
+  hipStreamSynchronize(c->stream);
+  for (size_t k = 0; k < c->allocs.size(); ++k)
+    if (c->allocs[k] == p) {
+      c->allocs.erase(c->allocs.begin() + k);
+      break;
+    }
+  if (c->dfree) c->dfree(p, c->actx);
+  else hipFree(p);
 }
 
 template <class T>
@@ -137,7 +160,7 @@ PhysArgs phys(const lbm_ctx *c, int l) {
   ph.fallback_tol = c->p.fallback_tol;
   ph.newton_max_it = c->p.newton_max_it;
   ph.warm = c->p.lambda_warm_start;
-  ph.mlp = nullptr;
+  ph.mlp = c->d_mlp_ops;
   return ph;
 }
 
@@ -332,6 +355,35 @@ lbm_status need_state(lbm_ctx *c) {
   return LBM_OK;
 }
 
+lbm_status mlp_ensure(lbm_ctx *c) {
+  if (c->p.host_only) return set_err(c, LBM_E_STATE, "context is host-only");
+  if (c->lat.kind != LAT_D2Q21) return set_err(c, LBM_E_ARG, "the multiplier surrogate needs a D2Q21 context");
+  if (c->d_mlp_w) return LBM_OK;
+  c->d_mlp_w = (float *)dev_alloc(c, sizeof(float) * MLP_PARAMS);
+  c->d_mlp_m = (float *)dev_alloc(c, sizeof(float) * MLP_PARAMS);
+  c->d_mlp_v = (float *)dev_alloc(c, sizeof(float) * MLP_PARAMS);
+  c->d_mlp_g = (float *)dev_alloc(c, sizeof(float) * MLP_PARAMS);
+  c->d_mlp_loss = (float *)dev_alloc(c, sizeof(float) * 64);
+  c->d_mlp_ops = dev_alloc(c, mlp_operands_bytes());
+  if (!c->d_mlp_w || !c->d_mlp_m || !c->d_mlp_v || !c->d_mlp_g || !c->d_mlp_ops || !c->d_mlp_loss)
+    return set_err(c, LBM_E_NOMEM, "surrogate allocation failed");
+  HIP_TRY(c, hipMemsetAsync(c->d_mlp_ops, 0, mlp_operands_bytes(), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_mlp_m, 0, sizeof(float) * MLP_PARAMS, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_mlp_v, 0, sizeof(float) * MLP_PARAMS, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_mlp_g, 0, sizeof(float) * MLP_PARAMS, c->stream));
+  return LBM_OK;
+}
+
+lbm_status mlp_upload_weights(lbm_ctx *c, const float *w) {
+  HIP_TRY(c, hipMemcpyAsync(c->d_mlp_w, w, sizeof(float) * MLP_PARAMS, hipMemcpyHostToDevice, c->stream));
+  mlp_operands(c->d_mlp_w, c->d_mlp_ops, c->stream);
+  lbm_status s = check_launch(c);
+  if (s != LBM_OK) return s;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->have_mlp = true;
+  return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -473,7 +525,17 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
     }
   }
   lbm_status s;
-  if ((s = upload(c, &c->d_flags, c->g.flag.data(), c->N)) != LBM_OK) return s;
+  {
+    // device flags: the canonical ones plus F_MOVING where a population is
+    // pulled from a moving wall
+    std::vector<uint8_t> fl(c->g.flag);
+    const int64_t N = c->N;
+#pragma omp parallel for schedule(static)
+    for (int64_t cc = 0; cc < N; ++cc)
+      for (int i = 0; i < Qm; ++i)
+        if (c->g.nbr[(size_t)i * N + cc] <= -3) fl[cc] |= F_MOVING;
+    if ((s = upload(c, &c->d_flags, fl.data(), c->N)) != LBM_OK) return s;
+  }
   if (!c->g.sigma.empty()) {
     if ((s = upload(c, &c->d_sigma, c->g.sigma.data(), c->N)) != LBM_OK) return s;
     if ((s = upload(c, &c->d_rhoinf, c->g.rho_inf.data(), c->N)) != LBM_OK) return s;
@@ -592,6 +654,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t n) {
   lbm_status s = need_state(c);
   if (s != LBM_OK) return s;
   if (n < 0) return set_err(c, LBM_E_ARG, "negative step count");
+  if (c->p.collision >= LBM_DDF_MLP && !c->have_mlp) return set_err(c, LBM_E_STATE, "surrogate weights not set");
   const int L = c->L;
   for (int64_t st = 0; st < n; ++st) {
     for (int t = 0; t < (1 << (L - 1)); ++t) {
@@ -716,6 +779,180 @@ lbm_status lbm_sync(lbm_ctx *c) {
 lbm_status lbm_profile_enable(lbm_ctx *c, int on) {
   if (!c) return LBM_E_ARG;
   c->prof = on != 0;
+  if (c->prof)
+    for (int l = 0; l < 8; ++l) {
+      c->prof_launches[l] = 0;
+      c->prof_ms[l] = 0.0;
+    }
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_set_weights(lbm_ctx *c, const float *w, int64_t n) {
+  if (!c || !w) return LBM_E_ARG;
+  if (n != MLP_PARAMS) return set_err(c, LBM_E_ARG, "expected 9176 packed parameters");
+  lbm_status s = mlp_ensure(c);
+  if (s != LBM_OK) return s;
+  return mlp_upload_weights(c, w);
+}
+
+lbm_status lbm_mlp_get_weights(lbm_ctx *c, float *w, int64_t n) {
+  if (!c || !w) return LBM_E_ARG;
+  if (n != MLP_PARAMS) return set_err(c, LBM_E_ARG, "expected 9176 packed parameters");
+  if (!c->have_mlp) return set_err(c, LBM_E_STATE, "surrogate weights not set");
+  HIP_TRY(c, hipMemcpyAsync(w, c->d_mlp_w, sizeof(float) * MLP_PARAMS, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_label(lbm_ctx *c, const double *x, int64_t n, double *lambda, uint8_t *ok, int32_t *iters) {
+  if (!c || !x || !lambda || !ok || n < 0) return LBM_E_ARG;
+  lbm_status s = mlp_ensure(c);
+  if (s != LBM_OK) return s;
+  if (n == 0) return LBM_OK;
+  double *dx = (double *)dev_alloc(c, sizeof(double) * 4 * n);
+  double *dl = (double *)dev_alloc(c, sizeof(double) * 8 * n);
+  uint8_t *dok = (uint8_t *)dev_alloc(c, n);
+  int *dit = (int *)dev_alloc(c, sizeof(int) * n);
+  if (!dx || !dl || !dok || !dit) return set_err(c, LBM_E_NOMEM, "label allocation failed");
+  HIP_TRY(c, hipMemcpyAsync(dx, x, sizeof(double) * 4 * n, hipMemcpyHostToDevice, c->stream));
+  mlp_label(dx, n, c->p.newton_tol, c->p.newton_max_it, dl, dok, dit, c->stream);
+  if ((s = check_launch(c)) != LBM_OK) return s;
+  HIP_TRY(c, hipMemcpyAsync(lambda, dl, sizeof(double) * 8 * n, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(ok, dok, n, hipMemcpyDeviceToHost, c->stream));
+  if (iters) HIP_TRY(c, hipMemcpyAsync(iters, dit, sizeof(int) * n, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  dev_release(c, dx);
+  dev_release(c, dl);
+  dev_release(c, dok);
+  dev_release(c, dit);
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_predict(lbm_ctx *c, const double *x, int64_t n, double *lambda) {
+  if (!c || !x || !lambda || n < 0) return LBM_E_ARG;
+  if (!c->have_mlp) return set_err(c, LBM_E_STATE, "surrogate weights not set");
+  if (n == 0) return LBM_OK;
+  double *dx = (double *)dev_alloc(c, sizeof(double) * 4 * n);
+  double *dl = (double *)dev_alloc(c, sizeof(double) * 8 * n);
+  if (!dx || !dl) return set_err(c, LBM_E_NOMEM, "prediction allocation failed");
+  HIP_TRY(c, hipMemcpyAsync(dx, x, sizeof(double) * 4 * n, hipMemcpyHostToDevice, c->stream));
+  mlp_predict(c->d_mlp_ops, dx, n, dl, c->stream);
+  lbm_status s = check_launch(c);
+  if (s != LBM_OK) return s;
+  HIP_TRY(c, hipMemcpyAsync(lambda, dl, sizeof(double) * 8 * n, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  dev_release(c, dx);
+  dev_release(c, dl);
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_grad(lbm_ctx *c, const float *xh, const float *th, int64_t n, double *loss, float *grad) {
+  if (!c || !xh || !th || !grad || n <= 0 || n % 32) return set_err(c, LBM_E_ARG, "bad batch");
+  if (!c->have_mlp) return set_err(c, LBM_E_STATE, "surrogate weights not set");
+  float *dx = (float *)dev_alloc(c, sizeof(float) * 4 * n);
+  float *dt = (float *)dev_alloc(c, sizeof(float) * 8 * n);
+  int32_t *dp = (int32_t *)dev_alloc(c, sizeof(int32_t) * n);
+  if (!dx || !dt || !dp) return set_err(c, LBM_E_NOMEM, "gradient allocation failed");
+  std::vector<int32_t> perm(n);
+  for (int64_t k = 0; k < n; ++k) perm[k] = (int32_t)k;
+  HIP_TRY(c, hipMemcpyAsync(dx, xh, sizeof(float) * 4 * n, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(dt, th, sizeof(float) * 8 * n, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(dp, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_mlp_g, 0, sizeof(float) * MLP_PARAMS, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_mlp_loss, 0, sizeof(float), c->stream));
+  mlp_train_batch(c->d_mlp_ops, dx, dt, dp, 0, n, c->d_mlp_g, c->d_mlp_loss, c->stream);
+  lbm_status s = check_launch(c);
+  if (s != LBM_OK) return s;
+  float lh = 0.0f;
+  HIP_TRY(c, hipMemcpyAsync(grad, c->d_mlp_g, sizeof(float) * MLP_TRAINABLE, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&lh, c->d_mlp_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_mlp_g, 0, sizeof(float) * MLP_PARAMS, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (loss) *loss = lh;
+  dev_release(c, dx);
+  dev_release(c, dt);
+  dev_release(c, dp);
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_train(lbm_ctx *c, const double *x, const double *lambda, int64_t n, int epochs, int batch,
+                         double lr, uint64_t seed, double *epoch_loss) {
+  if (!c || !x || !lambda || n <= 0 || epochs < 0 || batch <= 0 || batch % 32 || n < batch)
+    return set_err(c, LBM_E_ARG, "bad training arguments");
+  lbm_status s = mlp_ensure(c);
+  if (s != LBM_OK) return s;
+  std::mt19937_64 rng(seed);
+  std::vector<float> w(MLP_PARAMS, 0.0f);
+  if (c->have_mlp) {
+    HIP_TRY(c, hipMemcpy(w.data(), c->d_mlp_w, sizeof(float) * MLP_PARAMS, hipMemcpyDeviceToHost));
+  } else {
+    // uniform initialisation scaled by the fan-in; biases zero
+    const int offs[4] = {0, 320, 4480, 8640}, fan[4] = {4, 64, 64, 64}, cnt[4] = {256, 4096, 4096, 512};
+    for (int k = 0; k < 4; ++k) {
+      std::uniform_real_distribution<double> U(-1.0, 1.0);
+      const double lim = 0.5 * std::sqrt(6.0 / fan[k]);
+      for (int q = 0; q < cnt[k]; ++q) w[offs[k] + q] = (float)(lim * U(rng));
+    }
+  }
+  // output normalisation from the labels
+  double mu[8] = {0}, sg[8] = {0};
+  for (int64_t i = 0; i < n; ++i)
+    for (int k = 0; k < 8; ++k) mu[k] += lambda[i * 8 + k];
+  for (int k = 0; k < 8; ++k) mu[k] /= (double)n;
+  for (int64_t i = 0; i < n; ++i)
+    for (int k = 0; k < 8; ++k) sg[k] += (lambda[i * 8 + k] - mu[k]) * (lambda[i * 8 + k] - mu[k]);
+  for (int k = 0; k < 8; ++k) {
+    sg[k] = std::sqrt(sg[k] / (double)n);
+    if (!(sg[k] > 1e-12)) sg[k] = 1.0;
+    w[9160 + k] = (float)mu[k];
+    w[9168 + k] = (float)sg[k];
+  }
+  if ((s = mlp_upload_weights(c, w.data())) != LBM_OK) return s;
+  std::vector<float> xh(4 * n), th(8 * n);
+  for (int64_t i = 0; i < n; ++i) {
+    xh[4 * i] = (float)((x[4 * i] - 2.6) / 2.4);
+    xh[4 * i + 1] = (float)(x[4 * i + 1] / 2.5);
+    xh[4 * i + 2] = (float)(x[4 * i + 2] / 2.5);
+    xh[4 * i + 3] = (float)((x[4 * i + 3] - 1.75) / 1.25);
+    for (int k = 0; k < 8; ++k) th[8 * i + k] = (float)((lambda[8 * i + k] - mu[k]) / sg[k]);
+  }
+  float *dx = (float *)dev_alloc(c, sizeof(float) * 4 * n);
+  float *dt = (float *)dev_alloc(c, sizeof(float) * 8 * n);
+  int32_t *dp = (int32_t *)dev_alloc(c, sizeof(int32_t) * n);
+  if (!dx || !dt || !dp) return set_err(c, LBM_E_NOMEM, "training allocation failed");
+  HIP_TRY(c, hipMemcpyAsync(dx, xh.data(), sizeof(float) * 4 * n, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(dt, th.data(), sizeof(float) * 8 * n, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_mlp_m, 0, sizeof(float) * MLP_PARAMS, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_mlp_v, 0, sizeof(float) * MLP_PARAMS, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_mlp_g, 0, sizeof(float) * MLP_PARAMS, c->stream));
+  const int64_t nb = n / batch;
+  const int64_t total = nb * epochs;
+  std::vector<int32_t> perm(n);
+  int t = 0;
+  for (int e = 0; e < epochs; ++e) {
+    for (int64_t k = 0; k < n; ++k) perm[k] = (int32_t)k;
+    for (int64_t k = n - 1; k > 0; --k) {
+      std::uniform_int_distribution<int64_t> D(0, k);
+      std::swap(perm[k], perm[D(rng)]);
+    }
+    HIP_TRY(c, hipMemcpyAsync(dp, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d_mlp_loss, 0, sizeof(float), c->stream));
+    for (int64_t b = 0; b < nb; ++b) {
+      ++t;
+      const double frac = (double)(t - 1) / (double)std::max<int64_t>(total, 1);
+      const float lr_t = (float)(lr * (0.01 + 0.99 * 0.5 * (1.0 + std::cos(3.14159265358979323846 * frac))));
+      mlp_train_batch(c->d_mlp_ops, dx, dt, dp, b * batch, batch, c->d_mlp_g, c->d_mlp_loss, c->stream);
+      mlp_adam(c->d_mlp_w, c->d_mlp_m, c->d_mlp_v, c->d_mlp_g, c->d_mlp_ops, lr_t, t, c->stream);
+    }
+    if ((s = check_launch(c)) != LBM_OK) return s;
+    float lh = 0.0f;
+    HIP_TRY(c, hipMemcpyAsync(&lh, c->d_mlp_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (epoch_loss) epoch_loss[e] = lh / (double)nb;
+  }
+  dev_release(c, dx);
+  dev_release(c, dt);
+  dev_release(c, dp);
   return LBM_OK;
 }
 

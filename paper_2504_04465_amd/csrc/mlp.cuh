@@ -1,0 +1,136 @@
+// mlp.cuh -- the multiplier surrogate on BF16 matrix cores (gfx950).
+//
+// Network 4 -> 64 -> 64 -> 64 -> 8, SiLU hidden layers, linear output, on
+// normalised inputs ((rho - 2.6)/2.4, u_x/2.5, u_y/2.5, (T - 1.75)/1.25) and
+// outputs (lambda = mu + sigma * y).  One wavefront evaluates a tile of 32
+// samples with v_mfma_f32_32x32x16_bf16 (FP32 accumulation):
+//   A operand, lane l: row l % 32, k = 8 (l / 32) + j   (8 bf16)
+//   B operand, lane l: k = 8 (l / 32) + j, column l % 32 (8 bf16)
+//   C, lane l, register r: row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
+// Inputs enter as a high + low BF16 pair (columns 0-3 and 4-7 of a 16-wide
+// K block that shares the first-layer weights), so they keep ~16 bits.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ops.h"
+
+namespace lbm {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// packed FP32 master parameters (floats)
+constexpr int MW1 = 0, MB1 = 256, MW2 = 320, MB2 = 4416, MW3 = 4480, MB3 = 8576, MW4 = 8640,
+              MB4 = 9152, MMU = 9160, MSIG = 9168, MLP_NPARAM = 9176, MLP_NTRAIN = 9160;
+
+// BF16 operand copies derived from the master parameters
+struct MlpOperands {
+  __bf16 w1[64 * 16];   // [out][16]: W1 in columns 0-3 and again in 4-7
+  __bf16 w2[64 * 64];   // [out][in]
+  __bf16 w3[64 * 64];
+  __bf16 w4[32 * 64];   // [out 32, 8 used][in]
+  __bf16 w2t[64 * 64];  // [in][out]
+  __bf16 w3t[64 * 64];
+  __bf16 w4t[64 * 16];  // [in][out 16, 8 used]
+  float b1[64], b2[64], b3[64], b4[32];
+  float mu[8], sig[8];
+};
+
+__device__ inline f32x16 mfma32(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ inline int c_row(int l, int r) { return ((r >> 2) << 3) + ((l >> 5) << 2) + (r & 3); }
+
+__device__ inline float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+__device__ inline float dsilu_f(float z) {
+  const float s = 1.0f / (1.0f + __expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+// acc(32 x 32) = A[32 x K] (LDS row-major, lda) * B, with B[k][n] = W[n0 + n][k]
+// (W row-major in global memory, ldw)
+template <int K>
+__device__ inline f32x16 gemm_aw(const __bf16 *A, int lda, const __bf16 *W, int ldw, int n0) {
+  const int l = threadIdx.x & 63;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const bf16x8 a = *(const bf16x8 *)(A + (l & 31) * lda + k0 + 8 * (l >> 5));
+    const bf16x8 b = *(const bf16x8 *)(W + (n0 + (l & 31)) * ldw + k0 + 8 * (l >> 5));
+    acc = mfma32(a, b, acc);
+  }
+  return acc;
+}
+
+// split one normalised input row into the high / low BF16 columns
+__device__ inline void mlp_input_row(__bf16 *xin_row, float rho, float ux, float uy, float T) {
+  const float x[4] = {(rho - 2.6f) / 2.4f, ux / 2.5f, uy / 2.5f, (T - 1.75f) / 1.25f};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const __bf16 hi = (__bf16)x[k];
+    xin_row[k] = hi;
+    xin_row[4 + k] = (__bf16)(x[k] - (float)hi);
+  }
+#pragma unroll
+  for (int k = 8; k < 16; ++k) xin_row[k] = (__bf16)0.0f;
+}
+
+// forward of one 32-sample tile held by one wavefront.  xin [32][16],
+// ha / hb [32][64] scratch, y [32][8] output (normalised), z (optional,
+// training) [3][32][64] pre-activations, h (optional) keeps h1..h3 in
+// ha, hb, hc for the backward pass.  Every thread of the block must call it.
+__device__ inline void mlp_forward_tile(const MlpOperands *P, const __bf16 *xin, __bf16 *h1,
+                                        __bf16 *h2, __bf16 *h3, float *y, float *z) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int n0 = 0; n0 < 64; n0 += 32) {
+    const f32x16 acc = gemm_aw<16>(xin, 16, P->w1, 16, n0);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = c_row(l, r), col = n0 + (l & 31);
+      const float v = acc[r] + P->b1[col];
+      if (z) z[row * 64 + col] = v;
+      h1[row * 64 + col] = (__bf16)silu_f(v);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int n0 = 0; n0 < 64; n0 += 32) {
+    const f32x16 acc = gemm_aw<64>(h1, 64, P->w2, 64, n0);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = c_row(l, r), col = n0 + (l & 31);
+      const float v = acc[r] + P->b2[col];
+      if (z) z[2048 + row * 64 + col] = v;
+      h2[row * 64 + col] = (__bf16)silu_f(v);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int n0 = 0; n0 < 64; n0 += 32) {
+    const f32x16 acc = gemm_aw<64>(h2, 64, P->w3, 64, n0);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = c_row(l, r), col = n0 + (l & 31);
+      const float v = acc[r] + P->b3[col];
+      if (z) z[4096 + row * 64 + col] = v;
+      h3[row * 64 + col] = (__bf16)silu_f(v);
+    }
+  }
+  __syncthreads();
+  {
+    const f32x16 acc = gemm_aw<64>(h3, 64, P->w4, 64, 0);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = c_row(l, r), col = l & 31;
+      if (col < 8) y[row * 8 + col] = acc[r] + P->b4[col];
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace lbm

@@ -32,7 +32,7 @@ struct PhysArgs {
   int sensor_on, trace_eq;
   double newton_tol, fallback_tol;
   int newton_max_it, warm;
-  const float *mlp;    // packed MLP parameters (device), or null
+  const void *mlp;     // MLP operand block (device), or null
 };
 
 // collide-and-stream of the cells [begin, begin + count) of one level

@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "liblbm.so")
+# LBM_LIB_PATH selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("LBM_LIB_PATH", os.path.join(PKG, "liblbm.so"))
 
 LATTICES = {"D2Q9": 0, "D3Q27": 1, "D2Q21": 2, "D2Q37": 3}
 COLLISIONS = {"BGK": 0, "RR": 1, "DDF_POLY": 2, "DDF_NEWTON": 3, "DDF_MLP": 4, "DDF_MLP_NEWTON": 5}
@@ -25,7 +26,9 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_MASK", -3: "LBM_E_NOMEM", -4:
 EXPORTS = ["lbm_create", "lbm_grid_build", "lbm_grid_info", "lbm_grid_export", "lbm_init",
            "lbm_step", "lbm_set_face_bc", "lbm_moments", "lbm_moments_device", "lbm_stats_get",
            "lbm_sync", "lbm_profile_enable", "lbm_profile_read", "lbm_get_state", "lbm_set_state",
-           "lbm_last_error", "lbm_destroy"]
+           "lbm_last_error", "lbm_destroy", "lbm_mlp_set_weights", "lbm_mlp_get_weights",
+           "lbm_mlp_label", "lbm_mlp_predict", "lbm_mlp_grad", "lbm_mlp_train"]
+MLP_PARAMS = 9176
 
 
 class LbmError(RuntimeError):
@@ -94,6 +97,12 @@ def lib():
         L.lbm_last_error.restype = C.c_char_p
         L.lbm_last_error.argtypes = [vp]
         L.lbm_destroy.argtypes = [vp]
+        L.lbm_mlp_set_weights.argtypes = [vp, vp, i64]
+        L.lbm_mlp_get_weights.argtypes = [vp, vp, i64]
+        L.lbm_mlp_label.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.lbm_mlp_predict.argtypes = [vp, vp, i64, vp]
+        L.lbm_mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.lbm_mlp_train.argtypes = [vp, vp, vp, i64, C.c_int, C.c_int, C.c_double, C.c_uint64, vp]
         _lib = L
     return _lib
 
@@ -311,3 +320,46 @@ class LBM:
         g = None if g is None else np.ascontiguousarray(g, dtype=np.float64)
         lam = None if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
         self._check(self._L.lbm_set_state(self.h, _ptr(f), _ptr(g), _ptr(lam)), "lbm_set_state")
+
+    # ---- multiplier surrogate (D2Q21) ------------------------------------
+    def mlp_set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._check(self._L.lbm_mlp_set_weights(self.h, _ptr(w), w.size), "lbm_mlp_set_weights")
+
+    def mlp_get_weights(self):
+        w = np.zeros(MLP_PARAMS, np.float32)
+        self._check(self._L.lbm_mlp_get_weights(self.h, _ptr(w), w.size), "lbm_mlp_get_weights")
+        return w
+
+    def mlp_label(self, x):
+        """Newton (cold start) multipliers of states x [n, 4] = (rho, ux, uy, T)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        n = x.shape[0]
+        lam = np.zeros((n, 8))
+        ok = np.zeros(n, np.uint8)
+        it = np.zeros(n, np.int32)
+        self._check(self._L.lbm_mlp_label(self.h, _ptr(x), n, _ptr(lam), _ptr(ok), _ptr(it)), "lbm_mlp_label")
+        return lam, ok.astype(bool), it
+
+    def mlp_predict(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        lam = np.zeros((x.shape[0], 8))
+        self._check(self._L.lbm_mlp_predict(self.h, _ptr(x), x.shape[0], _ptr(lam)), "lbm_mlp_predict")
+        return lam
+
+    def mlp_grad(self, xh, th):
+        xh = np.ascontiguousarray(xh, dtype=np.float32)
+        th = np.ascontiguousarray(th, dtype=np.float32)
+        g = np.zeros(MLP_PARAMS - 16, np.float32)
+        loss = C.c_double()
+        self._check(self._L.lbm_mlp_grad(self.h, _ptr(xh), _ptr(th), xh.shape[0], C.byref(loss), _ptr(g)),
+                    "lbm_mlp_grad")
+        return loss.value, g
+
+    def mlp_train(self, x, lam, epochs=20, batch=1024, lr=2e-3, seed=5):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        hist = np.zeros(epochs)
+        self._check(self._L.lbm_mlp_train(self.h, _ptr(x), _ptr(lam), x.shape[0], epochs, batch, lr, seed,
+                                          _ptr(hist)), "lbm_mlp_train")
+        return hist

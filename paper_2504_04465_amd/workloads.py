@@ -370,6 +370,20 @@ def shear(n: int = 32, levels: int = 2, lattice: str = "D2Q9", collision: str = 
                     storage=storage)
 
 
+# --------------------------------------------------------------------------
+# training states of the multiplier surrogate
+# --------------------------------------------------------------------------
+def mlp_samples(n: int, seed: int = 5, rho=(0.2, 5.0), umax: float = 2.5, T=(0.5, 3.0)) -> np.ndarray:
+    """n states (rho, u_x, u_y, T): rho and T uniform on their ranges, u
+    uniform over the disc |u| <= umax (area-uniform radius)."""
+    ids = np.arange(n, dtype=np.int64)
+    a = [(uniform_noise(seed, ids, k, 1.0) + 1.0) * 0.5 for k in range(4)]
+    r = umax * np.sqrt(a[1])
+    th = 2.0 * np.pi * a[2]
+    return np.stack([rho[0] + (rho[1] - rho[0]) * a[0], r * np.cos(th), r * np.sin(th),
+                     T[0] + (T[1] - T[0]) * a[3]], axis=1)
+
+
 REGISTRY = {
     "cavity": cavity,
     "cylinder": cylinder,
