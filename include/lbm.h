@@ -147,7 +147,7 @@ lbm_status lbm_grid_build(lbm_ctx *ctx, int dim, const int32_t ext_coarse[3],
                           const lbm_mask *solid, const lbm_face_bc faces[6]);
 
 /* Cell counts; n_per_level has n_levels entries.  eq_fine_cells is
- * sum_l n_l / 2^(L-1-l) (Sec. 7.3, "equivalent fine cells").  Any output
+ * sum_l n_l / 2^(L-1-l) (Sec. 7.5, "equivalent fine cells").  Any output
  * pointer may be NULL. */
 lbm_status lbm_grid_info(lbm_ctx *ctx, int64_t *n_cells, int64_t *n_per_level,
                          int64_t *n_coarse_ghosts, double *eq_fine_cells);
@@ -225,7 +225,10 @@ lbm_status lbm_set_state(lbm_ctx *ctx, const double *f, const double *g,
  * FP32 accumulation and FP32 master weights (Adam).  Packed parameters, 9176
  * floats: W1[64][4] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[8][64]
  * b4[8] mu[8] sigma[8]; inputs are normalised as ((rho-2.6)/2.4, u_x/2.5,
- * u_y/2.5, (T-1.75)/1.25), outputs as lambda = mu + sigma * y.  Host arrays
+ * u_y/2.5, (T-1.75)/1.25), outputs as lambda = mu + sigma * y.  The network
+ * is evaluated on the canonical state u_x >= u_y >= 0; the multipliers of
+ * any state follow from the lattice's reflection symmetry (x / y swap and sign
+ * flips of the odd multipliers), so predictions are exactly symmetric.  Host arrays
  * are row-major per sample.  LBM_E_ARG when the context is not D2Q21, or a
  * size is not a multiple of 32 where one is required. */
 enum { LBM_MLP_PARAMS = 9176 };

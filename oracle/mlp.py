@@ -64,11 +64,45 @@ def forward(p, xh):
     return y, (xh, z1, h1, z2, h2, z3, h3)
 
 
+def canonicalize(x, lam=None):
+    """map states to the octant u_x >= u_y >= 0 by the reflections of the
+    lattice; the multipliers transform with them (x <-> y exchange of the
+    components, sign of the components odd in x or y).  Returns the mapped
+    states, mapped multipliers (if given) and the inverse map."""
+    x = np.array(x, dtype=np.float64)
+    sx, sy = x[:, 1] < 0, x[:, 2] < 0
+    x[:, 1], x[:, 2] = np.abs(x[:, 1]), np.abs(x[:, 2])
+    sw = x[:, 2] > x[:, 1]
+    x[sw, 1], x[sw, 2] = x[sw, 2].copy(), x[sw, 1].copy()
+
+    def flip(l):
+        l = np.array(l, dtype=np.float64)
+        for m, idx in [(sx, [1, 4, 6]), (sy, [2, 4, 7])]:
+            for k in idx:
+                l[m, k] = -l[m, k]
+        for a, b in [(1, 2), (3, 5), (6, 7)]:
+            l[sw, a], l[sw, b] = l[sw, b].copy(), l[sw, a].copy()
+        return l
+
+    def unflip(l):
+        l = np.array(l, dtype=np.float64)
+        for a, b in [(1, 2), (3, 5), (6, 7)]:
+            l[sw, a], l[sw, b] = l[sw, b].copy(), l[sw, a].copy()
+        for m, idx in [(sx, [1, 4, 6]), (sy, [2, 4, 7])]:
+            for k in idx:
+                l[m, k] = -l[m, k]
+        return l
+
+    return x, (None if lam is None else flip(lam)), unflip
+
+
 def predict(p, x):
-    """multipliers from macroscopic states [n, 4] (rho, u_x, u_y, T)."""
+    """multipliers from macroscopic states [n, 4] (rho, u_x, u_y, T): the
+    network is evaluated on the canonical state and mapped back."""
     P = unpack(p)
-    y, _ = forward(p, normalize_inputs(x))
-    return P["mu"] + P["sigma"] * y
+    xc, _, unflip = canonicalize(x)
+    y, _ = forward(p, normalize_inputs(xc))
+    return unflip(P["mu"] + P["sigma"] * y)
 
 
 HUBER = 0.5

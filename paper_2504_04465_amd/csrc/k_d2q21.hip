@@ -37,8 +37,9 @@ __global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
   }
   const bool collide = valid && !(fl & (F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ));
   // the multipliers depend on (u, T) only; non-colliding lanes feed a benign state
-  mlp_input_row(&xin[w][l >> 5][(l & 31) * 16], collide ? (float)rho : 1.0f, collide ? (float)u[0] : 0.0f,
-                collide ? (float)u[1] : 0.0f, collide ? (float)T : 1.0f);
+  float cux = collide ? (float)u[0] : 0.0f, cuy = collide ? (float)u[1] : 0.0f;
+  const Canon cn = canonical(cux, cuy);
+  mlp_input_row(&xin[w][l >> 5][(l & 31) * 16], collide ? (float)rho : 1.0f, cux, cuy, collide ? (float)T : 1.0f);
   __syncthreads();
   const MlpOperands *P = (const MlpOperands *)a.ph.mlp;
 #pragma unroll
@@ -47,6 +48,7 @@ __global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
     double lam[NLAM];
 #pragma unroll
     for (int k = 0; k < NLAM; ++k) lam[k] = (double)P->mu[k] + (double)P->sig[k] * (double)yb[w][l >> 5][(l & 31) * 8 + k];
+    uncanonical(cn, lam);
     C rhop = rho;
     if (fl & F_SPONGE) {
       const C s = (C)a.sigma[c];
@@ -59,11 +61,22 @@ __global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
     if constexpr (COLL == COLL_DDF_MLP_NEWTON) {
       const bool ok = newton_step<L>(lam, G, e, M);
       if (!ok || !(nrmmax_8(G) <= a.ph.fallback_tol)) {
+        // full Newton, continued from the corrected multipliers
         count_add(a.counters, CNT_MLP_FALLBACK, 1);
         count_add(a.counters, CNT_NEWTON_CALLS, 1);
-        const int it = newton_solve<L>((double)u[0], (double)u[1], (double)T, lam, a.ph.newton_tol,
-                                       a.ph.newton_max_it, e);
-        if (it < 0) count_add(a.counters, CNT_NEWTON_FAIL, 1);
+        int it = 0;
+        bool good = ok;
+        if (!ok) {
+#pragma unroll
+          for (int k = 0; k < NLAM; ++k) lam[k] = 0.0;
+          expo_residual<L>(lam, M, e, G);
+          good = true;
+        }
+        while (good && !(nrmmax_8(G) <= a.ph.newton_tol) && it < a.ph.newton_max_it) {
+          good = newton_step<L>(lam, G, e, M);
+          ++it;
+        }
+        if (!good || !(nrmmax_8(G) <= a.ph.newton_tol)) count_add(a.counters, CNT_NEWTON_FAIL, 1);
         else count_add(a.counters, CNT_NEWTON_ITERS, (unsigned long long)it);
       }
     }

@@ -894,6 +894,22 @@ lbm_status lbm_mlp_train(lbm_ctx *c, const double *x, const double *lambda, int6
       for (int q = 0; q < cnt[k]; ++q) w[offs[k] + q] = (float)(lim * U(rng));
     }
   }
+  // the network learns the canonical octant u_x >= u_y >= 0 (reflection
+  // symmetry of the lattice); map every sample and its label there
+  std::vector<double> xc(x, x + 4 * n), lc(lambda, lambda + 8 * n);
+  for (int64_t i = 0; i < n; ++i) {
+    double *xi = &xc[4 * i], *li = &lc[8 * i];
+    if (xi[1] < 0.0) { xi[1] = -xi[1]; li[1] = -li[1]; li[4] = -li[4]; li[6] = -li[6]; }
+    if (xi[2] < 0.0) { xi[2] = -xi[2]; li[2] = -li[2]; li[4] = -li[4]; li[7] = -li[7]; }
+    if (xi[2] > xi[1]) {
+      std::swap(xi[1], xi[2]);
+      std::swap(li[1], li[2]);
+      std::swap(li[3], li[5]);
+      std::swap(li[6], li[7]);
+    }
+  }
+  x = xc.data();
+  lambda = lc.data();
   // output normalisation from the labels
   double mu[8] = {0}, sg[8] = {0};
   for (int64_t i = 0; i < n; ++i)

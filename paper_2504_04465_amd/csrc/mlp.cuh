@@ -66,6 +66,35 @@ __device__ inline f32x16 gemm_aw(const __bf16 *A, int lda, const __bf16 *W, int 
   return acc;
 }
 
+// Reflection symmetry of the multipliers: the network sees the canonical
+// state u_x >= u_y >= 0; the multipliers of the actual state follow by
+// swapping the x / y components back and flipping the signs of the odd ones
+// (lambda order: 1, x, y, xx, xy, yy, x|xi|^2, y|xi|^2).
+struct Canon {
+  bool sx, sy, swap;
+};
+
+__device__ inline Canon canonical(float &ux, float &uy) {
+  Canon c;
+  c.sx = ux < 0.0f;
+  c.sy = uy < 0.0f;
+  float a = fabsf(ux), b = fabsf(uy);
+  c.swap = b > a;
+  ux = c.swap ? b : a;
+  uy = c.swap ? a : b;
+  return c;
+}
+
+__device__ inline void uncanonical(const Canon &c, double *lam) {
+  if (c.swap) {
+    double t = lam[1]; lam[1] = lam[2]; lam[2] = t;
+    t = lam[3]; lam[3] = lam[5]; lam[5] = t;
+    t = lam[6]; lam[6] = lam[7]; lam[7] = t;
+  }
+  if (c.sx) { lam[1] = -lam[1]; lam[4] = -lam[4]; lam[6] = -lam[6]; }
+  if (c.sy) { lam[2] = -lam[2]; lam[4] = -lam[4]; lam[7] = -lam[7]; }
+}
+
 // split one normalised input row into the high / low BF16 columns
 __device__ inline void mlp_input_row(__bf16 *xin_row, float rho, float ux, float uy, float T) {
   const float x[4] = {(rho - 2.6f) / 2.4f, ux / 2.5f, uy / 2.5f, (T - 1.75f) / 1.25f};

@@ -253,16 +253,20 @@ __global__ void __launch_bounds__(64) k_mlp_predict(const MlpOperands *P, const 
   __shared__ float y[32 * 8];
   const int l = threadIdx.x;
   const int64_t s = (int64_t)blockIdx.x * 32 + (l & 31);
-  if (l < 32) {
-    const bool ok = s < n;
-    mlp_input_row(xin + l * 16, ok ? (float)x[s * 4] : 1.0f, ok ? (float)x[s * 4 + 1] : 0.0f,
-                  ok ? (float)x[s * 4 + 2] : 0.0f, ok ? (float)x[s * 4 + 3] : 1.0f);
-  }
+  const bool ok = s < n;
+  float ux = ok ? (float)x[s * 4 + 1] : 0.0f, uy = ok ? (float)x[s * 4 + 2] : 0.0f;
+  const Canon cn = canonical(ux, uy);
+  if (l < 32) mlp_input_row(xin + l * 16, ok ? (float)x[s * 4] : 1.0f, ux, uy, ok ? (float)x[s * 4 + 3] : 1.0f);
   __syncthreads();
   mlp_forward_tile(P, xin, ha, hb, hc, y, nullptr);
-  if (l < 32 && s < n)
+  if (l < 32 && ok) {
+    double out[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) lam[s * 8 + k] = (double)P->mu[k] + (double)P->sig[k] * (double)y[l * 8 + k];
+    for (int k = 0; k < 8; ++k) out[k] = (double)P->mu[k] + (double)P->sig[k] * (double)y[l * 8 + k];
+    uncanonical(cn, out);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) lam[s * 8 + k] = out[k];
+  }
 }
 
 // ---------------------------------------------------------------------------

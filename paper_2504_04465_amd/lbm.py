@@ -6,8 +6,10 @@ is no fallback: if liblbm.so is missing or fails to load, this module raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -126,7 +128,7 @@ def face_struct(f) -> FaceBC:
 
 def equivalent_fine_cells(n_per_level) -> float:
     """sum_l n_l / 2^(L-1-l): cells weighted by their update frequency
-    relative to the finest level (Sec. 7.3)."""
+    relative to the finest level (Sec. 7.5)."""
     L = len(n_per_level)
     return float(sum(n / float(1 << (L - 1 - l)) for l, n in enumerate(n_per_level)))
 
@@ -147,6 +149,17 @@ class _TorchAlloc:
 
     def _free(self, ptr, _ctx):
         self.torch.cuda.caching_allocator_delete(ptr)
+
+
+# contexts still open at interpreter exit are destroyed while torch's
+# allocator (which owns their device memory) is still usable
+_LIVE: "weakref.WeakSet[LBM]" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for ctx in list(_LIVE):
+        ctx.close()
 
 
 class LBM:
@@ -181,6 +194,7 @@ class LBM:
         if rc != 0:
             raise LbmError(rc, f"lbm_create rejected {lattice}/{collision}/{storage}")
         self.h = h
+        _LIVE.add(self)
 
     @classmethod
     def from_workload(cls, w, storage=None, host_only=False, **over):
@@ -199,6 +213,7 @@ class LBM:
         if getattr(self, "h", None):
             self._L.lbm_destroy(self.h)
             self.h = None
+            _LIVE.discard(self)
 
     def _check(self, rc, what=""):
         if rc != 0:

@@ -40,6 +40,26 @@ def test_adam_step_formula():
 
 def test_prediction_denormalises():
     p = M.init_params(2, mu=np.arange(8.0), sigma=np.full(8, 2.0))
-    x = np.array([[1.0, 0.3, -0.2, 0.65]])
+    x = np.array([[1.0, 0.3, 0.2, 0.65]])  # already canonical (u_x >= u_y >= 0)
     y, _ = M.forward(p, M.normalize_inputs(x))
     assert np.allclose(M.predict(p, x), np.arange(8.0) + 2.0 * y)
+    # a reflected state: sign flips of the odd multipliers, nothing else
+    xr = np.array([[1.0, -0.3, 0.2, 0.65]])
+    flip = np.array([1, -1, 1, 1, -1, 1, -1, 1])
+    assert np.allclose(M.predict(p, xr), flip * (np.arange(8.0) + 2.0 * y))
+
+
+def test_canonical_map_is_the_lattice_symmetry():
+    """the reflection/swap map of the multipliers agrees with the oracle's
+    Newton solution at the mapped states (exact symmetry of Eq. exponential
+    on the D2Q21 lattice)"""
+    from oracle.oracle import Oracle
+    o = Oracle("D2Q21", "DDF_NEWTON", T0=0.65, gamma=1.4)
+    states = np.array([[1.0, -0.4, 0.7, 0.6], [1.0, 0.9, -0.3, 0.8], [1.0, -0.5, -0.6, 0.7]])
+    lam = np.array([o.newton(s[1:3], s[3])[1] for s in states])
+    xc, lc, unflip = M.canonicalize(states, lam)
+    assert np.all(xc[:, 1] >= xc[:, 2]) and np.all(xc[:, 2] >= 0)
+    for k in range(len(states)):
+        _, lref = o.newton(xc[k, 1:3], xc[k, 3])
+        assert np.max(np.abs(lc[k] - lref)) < 1e-9
+    assert np.max(np.abs(unflip(lc) - lam)) < 1e-15
