@@ -152,6 +152,18 @@ lbm_status lbm_grid_build(lbm_ctx *ctx, int dim, const int32_t ext_coarse[3],
 lbm_status lbm_grid_info(lbm_ctx *ctx, int64_t *n_cells, int64_t *n_per_level,
                          int64_t *n_coarse_ghosts, double *eq_fine_cells);
 
+/* Device placement of the grid (Sec. 4.4 gives the paper's own layout; this
+ * one differs): the cells of each level sit in bricks of 64 slots (4x4x4 in
+ * 3-D, 8x8 in 2-D) in Z order, one brick per wavefront.  A cell whose pull
+ * sources all follow from its brick's neighbour bricks reads no neighbour
+ * list; every other cell (ghosts, boundary layers, cells next to walls or
+ * bodies) has an explicit row of pull sources.  n_slots counts the slots of
+ * all levels including the unused ones of partly filled bricks;
+ * n_exception_rows the cells with an explicit row; slots_per_level and
+ * rows_per_level have n_levels entries.  Any output pointer may be NULL. */
+lbm_status lbm_layout_info(lbm_ctx *ctx, int64_t *n_slots, int64_t *n_exception_rows,
+                           int64_t *slots_per_level, int64_t *rows_per_level);
+
 /* Export the tables in canonical form (any pointer may be NULL):
  * coords [n][3], level [n], flags [n], nbr [n][Q-1] (sentinels above),
  * child [n_coarse_ghosts][2^D] (octant o = cx | cy<<1 | cz<<2, -1 missing),

@@ -19,6 +19,7 @@ enum NodeFlag : uint8_t {
   F_BC_EQ = 8,
   F_SPONGE = 16,
   F_MOVING = 32,  // device copy only: a population comes from a moving wall
+  F_HOLE = 64,    // device copy only: a slot of a brick without a cell
 };
 
 enum { NBR_NONE = -1, NBR_SOLID = -2 };  // moving wall on face k: -3 - k

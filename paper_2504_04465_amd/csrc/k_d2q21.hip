@@ -21,18 +21,20 @@ __global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
   __shared__ __align__(16) __bf16 ha[BLOCK / 64][32 * 64];
   __shared__ __align__(16) __bf16 hb[BLOCK / 64][32 * 64];
   __shared__ float yb[BLOCK / 64][2][32 * 8];
+  __shared__ uint32_t nbs[BLOCK / 64][Brick<L>::NBP];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t t = xcd_block() * BLOCK + threadIdx.x;
-  const bool valid = t < a.count;
-  const int64_t c = a.begin + (valid ? t : 0);
+  const bool live = t < a.count;  // whole wavefronts
+  const int64_t c = a.begin + (live ? t : 0);
+  const int32_t brick = stage_bricks<L, S>(a.topo, nbs, c, live);
+  const uint8_t fl = live ? a.flags[c] : (uint8_t)F_HOLE;
+  const bool valid = !(fl & F_HOLE);
   const int64_t stride = a.stride;
   C f[Q], g[Q];
-  uint8_t fl = 0;
   C rho = (C)1, u[3] = {(C)0, (C)0, (C)0}, T = (C)1;
   if (valid) {
-    fl = a.flags[c];
-    gather<L, S, PRE, true>((const S *)a.fin, (const S *)a.gin, a.nbr, stride, a.vbase, c, a.ph.uw, a.ph.cs2w,
-                            f, g);
+    gather<L, S, PRE, true>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[w], stride, a.vbase, c, l, brick,
+                            a.topo.xmask[brick], a.ph.uw, a.ph.cs2w, f, g);
     cell_moments<L, C, true>(f, g, (C)a.ph.Cv, rho, u, T);
   }
   const bool collide = valid && !(fl & (F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ));

@@ -36,12 +36,14 @@ template <>
 struct Sto<double> {
   using C = double;
   __device__ static C ld(const double *p, int64_t k, double) { return p[k]; }
+  __device__ static C ldv(double v, double) { return v; }
   __device__ static void st(double *p, int64_t k, C v, double) { p[k] = v; }
 };
 template <>
 struct Sto<float> {
   using C = float;
   __device__ static C ld(const float *p, int64_t k, double) { return p[k]; }
+  __device__ static C ldv(float v, double) { return v; }
   __device__ static void st(float *p, int64_t k, C v, double) { p[k] = v; }
 };
 template <>
@@ -50,6 +52,7 @@ struct Sto<__half> {
   __device__ static C ld(const __half *p, int64_t k, double w) {
     return __half2float(p[k]) + (float)w;
   }
+  __device__ static C ldv(__half v, double w) { return __half2float(v) + (float)w; }
   __device__ static void st(__half *p, int64_t k, C v, double w) {
     p[k] = __float2half_rn(v - (float)w);
   }
@@ -87,15 +90,16 @@ __device__ inline double wall_dot(const double (&uw)[6][3], int k, int i) {
 }
 
 // ---------------------------------------------------------------------------
-// pull of one population; PRE: the buffer still holds pre-collision values
-// (after initialisation or a state restore), so only coalesced slots move
+// pull of one population through an explicit row of pull sources; PRE: the
+// buffer still holds pre-collision values (after initialisation or a state
+// restore), so only coalesced slots move
 // ---------------------------------------------------------------------------
 template <class L, class S, bool PRE>
-__device__ inline typename Sto<S>::C pull_f(const S *fin, const int32_t *nbr, int64_t stride,
-                                            int64_t vbase, int64_t c, int i,
+__device__ inline typename Sto<S>::C pull_f(const S *fin, const int32_t *tab, int64_t tstride, int64_t row,
+                                            int64_t stride, int64_t vbase, int64_t c, int i,
                                             const double (&uw)[6][3], double cs2w) {
   using C = typename Sto<S>::C;
-  const int32_t s = nbr[(int64_t)(i - 1) * stride + c];
+  const int32_t s = tab[(int64_t)(i - 1) * tstride + row];
   if (PRE) {
     const int64_t src = ((int64_t)s >= vbase) ? (int64_t)s : c;
     return Sto<S>::ld(fin, (int64_t)i * stride + src, L::S.w[i]);
@@ -108,9 +112,9 @@ __device__ inline typename Sto<S>::C pull_f(const S *fin, const int32_t *nbr, in
 }
 
 template <class L, class S, bool PRE>
-__device__ inline typename Sto<S>::C pull_g(const S *gin, const int32_t *nbr, int64_t stride,
-                                            int64_t vbase, int64_t c, int i) {
-  const int32_t s = nbr[(int64_t)(i - 1) * stride + c];
+__device__ inline typename Sto<S>::C pull_g(const S *gin, const int32_t *tab, int64_t tstride, int64_t row,
+                                            int64_t stride, int64_t vbase, int64_t c, int i) {
+  const int32_t s = tab[(int64_t)(i - 1) * tstride + row];
   if (PRE) {
     const int64_t src = ((int64_t)s >= vbase) ? (int64_t)s : c;
     return Sto<S>::ld(gin, (int64_t)i * stride + src, 0.0);
@@ -119,17 +123,128 @@ __device__ inline typename Sto<S>::C pull_g(const S *gin, const int32_t *nbr, in
   return Sto<S>::ld(gin, (int64_t)L::S.opp[i] * stride + c, 0.0);
 }
 
+// ---------------------------------------------------------------------------
+// bricks: 64 cells (4x4x4 or 8x8) per wavefront, Z order inside the brick
+// ---------------------------------------------------------------------------
+template <class L>
+struct Brick {
+  static constexpr int SH = L::D == 3 ? 2 : 3;
+  static constexpr int BS = 1 << SH;
+  static constexpr int NB = L::D == 3 ? 27 : 9;
+  static constexpr int NBP = L::D == 3 ? 32 : 16;
+};
+
+// coordinate d of lane inside its brick
+template <class L>
+__device__ inline int lane_coord(int lane, int d) {
+  int r = 0;
+#pragma unroll
+  for (int b = 0; b < Brick<L>::SH; ++b) r |= ((lane >> (L::D * b + d)) & 1) << b;
+  return r;
+}
+
+// lane of local coordinate p (0 <= p < BS) along axis d
+template <class L>
+__device__ inline int lane_bits(int p, int d) {
+  int r = 0;
+#pragma unroll
+  for (int b = 0; b < Brick<L>::SH; ++b) r |= ((p >> b) & 1) << (L::D * b + d);
+  return r;
+}
+
+// Gather of the Q (2Q) populations a cell pulls (f_i from x - xi_i).
+//
+// Bulk lanes: the source of population i sits in the brick at offset
+// dir = sum_d w_d 3^d (w_d = 0, 1, 2 for a step to the lower neighbour, none,
+// the upper neighbour along d) at local coordinates (lc - xi_i) mod BS.  The
+// byte offset of every neighbour brick is staged in LDS (nbs); per lane and
+// axis the table K[d][xi_d] packs (LDS byte offset of the direction part) << 16
+// | (byte offset of the local coordinate part), so a population costs two
+// integer adds, an LDS read and a load with a 32-bit offset from the
+// population's base address.
+//
+// Lanes flagged in the brick's exception mask read their explicit row:
+// every source is loaded before any is used, so the loads overlap.
 template <class L, class S, bool PRE, bool DDF>
-__device__ inline void gather(const S *fin, const S *gin, const int32_t *nbr, int64_t stride,
-                              int64_t vbase, int64_t c, const double (&uw)[6][3], double cs2w,
-                              typename Sto<S>::C *f, typename Sto<S>::C *g) {
+__device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const uint32_t *nbs, int64_t stride,
+                              int64_t vbase, int64_t c, int lane, int32_t brick, uint64_t xm,
+                              const double (&uw)[6][3], double cs2w, typename Sto<S>::C *f,
+                              typename Sto<S>::C *g) {
+  using C = typename Sto<S>::C;
+  constexpr int BS = Brick<L>::BS, R = L::B, D = L::D;
   f[0] = Sto<S>::ld(fin, c, L::S.w[0]);
   if (DDF) g[0] = Sto<S>::ld(gin, c, 0.0);
+  if (!((xm >> lane) & 1ull)) {
+    if (PRE) {
 #pragma unroll
-  for (int i = 1; i < L::Q; ++i) {
-    f[i] = pull_f<L, S, PRE>(fin, nbr, stride, vbase, c, i, uw, cs2w);
-    if (DDF) g[i] = pull_g<L, S, PRE>(gin, nbr, stride, vbase, c, i);
+      for (int i = 1; i < L::Q; ++i) {
+        f[i] = Sto<S>::ld(fin, (int64_t)i * stride + c, L::S.w[i]);
+        if (DDF) g[i] = Sto<S>::ld(gin, (int64_t)i * stride + c, 0.0);
+      }
+      return;
+    }
+    uint32_t K[3][2 * R + 1];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int lc = d < D ? lane_coord<L>(lane, d) : 0;
+#pragma unroll
+      for (int x = -R; x <= R; ++x) {
+        if (d >= D) {
+          K[d][x + R] = 0u;
+          continue;
+        }
+        const int p = lc - x;
+        const uint32_t w = p < 0 ? 0u : (p >= BS ? 2u : 1u);
+        const uint32_t pw = d == 0 ? 1u : (d == 1 ? 3u : 9u);
+        K[d][x + R] = ((w * pw * 4u) << 16) | ((uint32_t)lane_bits<L>(p & (BS - 1), d) * (uint32_t)sizeof(S));
+      }
+    }
+    const char *fb = (const char *)fin;
+    const char *gb = (const char *)gin;
+    const int64_t pstride = stride * (int64_t)sizeof(S);
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+      const uint32_t k = K[0][cx_<L>(i, 0) + R] + K[1][cx_<L>(i, 1) + R] + K[2][cx_<L>(i, 2) + R];
+      const uint32_t off = nbs[k >> 18] + (k & 0xffffu);
+      f[i] = Sto<S>::ldv(*(const S *)(fb + i * pstride + off), L::S.w[i]);
+      if (DDF) g[i] = Sto<S>::ldv(*(const S *)(gb + i * pstride + off), 0.0);
+    }
+  } else {
+    const int64_t row = tp.xbase[brick] + __popcll(xm & ((1ull << lane) - 1ull));
+    int32_t sv[L::Q];
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) sv[i] = tp.xnbr[(int64_t)(i - 1) * tp.xstride + row];
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+      const int32_t s = sv[i];
+      int64_t idx;
+      if (PRE) idx = (int64_t)i * stride + ((int64_t)s >= vbase ? (int64_t)s : c);
+      else idx = s >= 0 ? (int64_t)i * stride + s : (int64_t)L::S.opp[i] * stride + c;
+      // the lattice is symmetric: w of the opposite population is w_i
+      f[i] = Sto<S>::ld(fin, idx, L::S.w[i]);
+      if (DDF) g[i] = Sto<S>::ld(gin, idx, 0.0);
+    }
+    if (!PRE) {
+#pragma unroll
+      for (int i = 1; i < L::Q; ++i)
+        if (sv[i] <= -2) f[i] += (C)(2.0 * L::S.w[i] * wall_dot<L>(uw, -2 - sv[i], i) / cs2w);
+    }
   }
+}
+
+// Per-block preamble of the kernels that gather: stages the byte offsets of
+// the neighbour bricks of the block's four bricks in LDS.  Every thread of
+// the block must call it.  Returns the wave-uniform brick id.
+template <class L, class S>
+__device__ inline int32_t stage_bricks(const Topo &tp, uint32_t (*nbs)[Brick<L>::NBP], int64_t c, bool live) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int32_t brick = __builtin_amdgcn_readfirstlane((int32_t)(c >> 6));
+  if (live && lane < Brick<L>::NB) {
+    const int32_t nb = tp.nbrick[(int64_t)brick * Brick<L>::NBP + lane];
+    nbs[w][lane] = nb < 0 ? 0u : (uint32_t)nb * (uint32_t)(64 * sizeof(S));
+  }
+  __syncthreads();
+  return brick;
 }
 
 // ---------------------------------------------------------------------------
@@ -550,21 +665,37 @@ __device__ inline void count_add(unsigned long long *ctr, int which, unsigned lo
 // ---------------------------------------------------------------------------
 // collide and stream (pull) for the cells [begin, begin + count) of a level
 // ---------------------------------------------------------------------------
+// Occupancy floor of the collide kernel: the single-population product
+// lattices are bound by memory latency and run best with at least six
+// wavefronts per SIMD (at most 85 VGPRs; four, 128 VGPRs, for FP64, which
+// would otherwise spill); the compute-heavy DDF models keep the compiler's
+// choice.
+template <class L, int COLL, class S>
+struct MinWaves {
+  static constexpr int value = COLL < COLL_DDF_POLY ? (sizeof(S) == 8 ? 4 : 6) : 1;
+};
+
 template <class L, int COLL, class S, bool PRE>
-__global__ void __launch_bounds__(BLOCK) k_collide(const KArgs a) {
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MinWaves<L, COLL, S>::value)))
+k_collide(const KArgs a) {
   using C = typename Sto<S>::C;
   constexpr bool DDF = COLL >= COLL_DDF_POLY;
   constexpr int Q = L::Q;
+  __shared__ uint32_t nbs[BLOCK / 64][Brick<L>::NBP];
   const int64_t t = xcd_block() * BLOCK + threadIdx.x;
-  if (t >= a.count) return;
-  const int64_t c = a.begin + t;
+  const bool live = t < a.count;  // whole wavefronts
+  const int64_t c = a.begin + (live ? t : 0);
+  const int32_t brick = stage_bricks<L, S>(a.topo, nbs, c, live);
+  if (!live) return;
+  const uint8_t fl = a.flags[c];
+  if (fl & F_HOLE) return;
   const int64_t stride = a.stride;
   const S *fin = (const S *)a.fin;
   const S *gin = (const S *)a.gin;
   C f[Q];
   C g[DDF ? Q : 1];
-  gather<L, S, PRE, DDF>(fin, gin, a.nbr, stride, a.vbase, c, a.ph.uw, a.ph.cs2w, f, g);
-  const uint8_t fl = a.flags[c];
+  gather<L, S, PRE, DDF>(fin, gin, a.topo, nbs[threadIdx.x >> 6], stride, a.vbase, c, threadIdx.x & 63, brick,
+                         a.topo.xmask[brick], a.ph.uw, a.ph.cs2w, f, g);
   if (!(fl & (F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ))) {
     C rho, u[3], T;
     cell_moments<L, C, DDF>(f, g, (C)a.ph.Cv, rho, u, T);
@@ -648,6 +779,7 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
   const bool valid = gl < a.count;
   const int64_t gk = a.g0 + gl;
   const int32_t ch = valid ? a.child[gk * NCH + (t % NCH)] : -1;
+  const int32_t crow = ch >= 0 ? a.crow[gk * NCH + (t % NCH)] : 0;
   const uint64_t mask = valid ? a.unknown[gk] : 0ull;
   const bool lead = valid && (t % NCH) == 0;
   const C nf = group_sum<NCH, C>(ch >= 0 ? (C)1 : (C)0);
@@ -661,8 +793,8 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
     const bool need = (mask >> i) & 1ull;
     C v = (C)0, vg = (C)0;
     if (need && ch >= 0) {
-      v = pull_f<L, S, PRE>(fin, a.nbr, a.stride, a.vbase, ch, i, a.uw, a.cs2w);
-      if (DDF) vg = pull_g<L, S, PRE>(gin, a.nbr, a.stride, a.vbase, ch, i);
+      v = pull_f<L, S, PRE>(fin, a.xnbr, a.xstride, crow, a.stride, a.vbase, ch, i, a.uw, a.cs2w);
+      if (DDF) vg = pull_g<L, S, PRE>(gin, a.xnbr, a.xstride, crow, a.stride, a.vbase, ch, i);
     }
     v = group_sum<NCH, C>(v);
     if (DDF) vg = group_sum<NCH, C>(vg);
@@ -787,38 +919,43 @@ template <class L, class S, bool PRE, bool DDF>
 __global__ void __launch_bounds__(BLOCK) k_gather(const MArgs a) {
   using C = typename Sto<S>::C;
   constexpr int Q = L::Q;
+  __shared__ uint32_t nbs[BLOCK / 64][Brick<L>::NBP];
   const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  const bool valid = t < a.count;
-  const int64_t c = a.begin + (valid ? t : 0);
+  const bool live = t < a.count;  // whole wavefronts
+  const int64_t c = a.begin + (live ? t : 0);
+  const int32_t brick = stage_bricks<L, S>(a.topo, nbs, c, live);
+  const int32_t cell = live ? a.cell_of[c] : -1;
+  const bool valid = cell >= 0;
   C f[Q];
   C g[DDF ? Q : 1];
   const bool fine_ghost = valid && (a.flags[c] & F_FINE_GHOST);
   if (valid)
-    gather<L, S, PRE, DDF>((const S *)a.fin, (const S *)a.gin, a.nbr, a.stride, a.vbase, c, a.uw,
-                           a.cs2w, f, g);
+    gather<L, S, PRE, DDF>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[threadIdx.x >> 6], a.stride, a.vbase,
+                           c, threadIdx.x & 63, brick, a.topo.xmask[brick], a.uw, a.cs2w, f, g);
   if (a.mode == 0) {
     if (!valid) return;
     const int nm = 1 + L::D + (DDF ? 1 : 0);
     if (fine_ghost) {
-      for (int k = 0; k < nm; ++k) a.out[(int64_t)k * a.n + c] = __longlong_as_double(0x7ff8000000000000ll);
+      for (int k = 0; k < nm; ++k) a.out[(int64_t)k * a.n + cell] = __longlong_as_double(0x7ff8000000000000ll);
       return;
     }
     C rho, u[3], T;
     cell_moments<L, C, DDF>(f, g, (C)a.Cv, rho, u, T);
-    a.out[c] = (double)rho;
-    for (int d = 0; d < L::D; ++d) a.out[(int64_t)(1 + d) * a.n + c] = (double)u[d];
-    if (DDF) a.out[(int64_t)(1 + L::D) * a.n + c] = (double)T;
+    a.out[cell] = (double)rho;
+    for (int d = 0; d < L::D; ++d) a.out[(int64_t)(1 + d) * a.n + cell] = (double)u[d];
+    if (DDF) a.out[(int64_t)(1 + L::D) * a.n + cell] = (double)T;
     return;
   }
   if (a.mode == 1) {
     if (!valid) return;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      a.out[(int64_t)i * a.n + c] = (double)f[i];
-      if (DDF) a.out[(int64_t)(Q + i) * a.n + c] = (double)g[i];
+      a.out[(int64_t)i * a.n + cell] = (double)f[i];
+      if (DDF) a.out[(int64_t)(Q + i) * a.n + cell] = (double)g[i];
     }
     if (a.lam_out)
-      for (int k = 0; k < NLAM; ++k) a.lam_out[(int64_t)k * a.n + c] = (double)a.lam[(int64_t)k * a.stride + c];
+      for (int k = 0; k < NLAM; ++k)
+        a.lam_out[(int64_t)k * a.n + cell] = (double)a.lam[(int64_t)k * a.stride + c];
     return;
   }
   // mode 2: volume-weighted conserved sums, deterministic block reduction
@@ -865,24 +1002,25 @@ __global__ void __launch_bounds__(BLOCK) k_init(const IArgs a) {
   using C = typename Sto<S>::C;
   constexpr bool DDF = COLL >= COLL_DDF_POLY;
   constexpr bool LAM = COLL >= COLL_DDF_NEWTON;
-  const int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (c >= a.n) return;
+  const int64_t k0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // canonical cell
+  if (k0 >= a.n) return;
+  const int64_t c = a.slot_of[k0];
   S *f = (S *)a.f;
   S *g = (S *)a.g;
   if (a.mode == 1) {
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-      Sto<S>::st(f, (int64_t)i * a.stride + c, (C)a.src[(int64_t)i * a.n + c], L::S.w[i]);
-      if (DDF) Sto<S>::st(g, (int64_t)i * a.stride + c, (C)a.src_g[(int64_t)i * a.n + c], 0.0);
+      Sto<S>::st(f, (int64_t)i * a.stride + c, (C)a.src[(int64_t)i * a.n + k0], L::S.w[i]);
+      if (DDF) Sto<S>::st(g, (int64_t)i * a.stride + c, (C)a.src_g[(int64_t)i * a.n + k0], 0.0);
     }
     if (LAM && a.src_lam)
-      for (int k = 0; k < NLAM; ++k) a.lam[(int64_t)k * a.stride + c] = (float)a.src_lam[(int64_t)k * a.n + c];
+      for (int k = 0; k < NLAM; ++k) a.lam[(int64_t)k * a.stride + c] = (float)a.src_lam[(int64_t)k * a.n + k0];
     return;
   }
-  const C rho = (C)a.src[c];
+  const C rho = (C)a.src[k0];
   C u[3] = {(C)0, (C)0, (C)0};
-  for (int d = 0; d < L::D; ++d) u[d] = (C)a.src[(int64_t)(1 + d) * a.n + c];
-  const C T = DDF ? (C)a.src[(int64_t)(1 + L::D) * a.n + c] : (C)0;
+  for (int d = 0; d < L::D; ++d) u[d] = (C)a.src[(int64_t)(1 + d) * a.n + k0];
+  const C T = DDF ? (C)a.src[(int64_t)(1 + L::D) * a.n + k0] : (C)0;
   C feq[L::Q], geq[DDF ? L::Q : 1];
   double lam[NLAM];
   const int it = equilibrium_any<L, COLL, C>(rho, u, T, a.ph, lam, false, feq, geq);

@@ -12,6 +12,7 @@
 
 #include "grid_builder.h"
 #include "lattice.h"
+#include "layout.h"
 #include "lbm.h"
 #include "mlp_ops.h"
 #include "ops.h"
@@ -38,14 +39,18 @@ struct lbm_ctx {
   // grid
   bool have_grid = false;
   HostGrid g;
+  DeviceLayout lay;
   lbm_face_bc face[6]{};
   int dim = 0, L = 0;
   double tau[8]{};
-  int64_t N = 0, Ng = 0, stride = 0;
+  double bpu[8]{};  // algorithmic bytes per cell update of the collide kernel, per level
+  int64_t N = 0, NS = 0, Ng = 0, stride = 0;  // cells, slots, coarse ghosts, SoA stride
   // device
   std::vector<void *> allocs;
   void *f[2]{}, *gb[2]{};
-  int32_t *d_nbr = nullptr;
+  int32_t *d_nbrick = nullptr, *d_xbase = nullptr, *d_xnbr = nullptr;
+  uint64_t *d_xmask = nullptr;
+  int32_t *d_cell_of = nullptr, *d_slot_of = nullptr, *d_crow = nullptr;
   uint8_t *d_flags = nullptr;
   double *d_sigma = nullptr, *d_rhoinf = nullptr;
   float *d_lam = nullptr;
@@ -109,7 +114,9 @@ void free_device(lbm_ctx *c) {
   }
   c->allocs.clear();
   c->f[0] = c->f[1] = c->gb[0] = c->gb[1] = nullptr;
-  c->d_nbr = nullptr;
+  c->d_nbrick = c->d_xbase = c->d_xnbr = nullptr;
+  c->d_xmask = nullptr;
+  c->d_cell_of = c->d_slot_of = c->d_crow = nullptr;
   c->d_flags = nullptr;
   c->d_sigma = c->d_rhoinf = nullptr;
   c->d_lam = nullptr;
@@ -167,6 +174,16 @@ PhysArgs phys(const lbm_ctx *c, int l) {
 const void *fbuf(const lbm_ctx *c, int l) { return c->f[c->parity[l]]; }
 const void *gbuf(const lbm_ctx *c, int l) { return c->gb[c->parity[l]]; }
 
+Topo topo(const lbm_ctx *c) {
+  Topo t{};
+  t.nbrick = c->d_nbrick;
+  t.xmask = c->d_xmask;
+  t.xbase = c->d_xbase;
+  t.xnbr = c->d_xnbr;
+  t.xstride = c->lay.xstride;
+  return t;
+}
+
 void launch_coalesce(lbm_ctx *c, int l) {
   const int64_t cnt = c->g.goff[l + 1] - c->g.goff[l];
   if (cnt <= 0) return;
@@ -177,9 +194,11 @@ void launch_coalesce(lbm_ctx *c, int l) {
   a.gout_coarse = const_cast<void *>(gbuf(c, l));
   a.lam = c->d_lam;
   a.stride = c->stride;
-  a.vbase = c->N;
-  a.nbr = c->d_nbr;
+  a.vbase = c->NS;
+  a.xnbr = c->d_xnbr;
+  a.xstride = c->lay.xstride;
   a.child = c->d_child;
+  a.crow = c->d_crow;
   a.unknown = c->d_unknown;
   a.ghost_cell = c->d_ghost;
   a.g0 = c->g.goff[l];
@@ -249,7 +268,7 @@ hipEvent_t take_event(lbm_ctx *c) {
 }
 
 void launch_collide(lbm_ctx *c, int l) {
-  const int64_t cnt = c->g.off[l + 1] - c->g.off[l];
+  const int64_t cnt = c->lay.soff[l + 1] - c->lay.soff[l];
   if (cnt > 0) {
     KArgs a{};
     a.fin = c->f[c->parity[l]];
@@ -257,13 +276,13 @@ void launch_collide(lbm_ctx *c, int l) {
     a.gin = c->gb[c->parity[l]];
     a.gout = c->gb[1 - c->parity[l]];
     a.stride = c->stride;
-    a.vbase = c->N;
-    a.nbr = c->d_nbr;
+    a.vbase = c->NS;
+    a.topo = topo(c);
     a.flags = c->d_flags;
     a.sigma = c->d_sigma;
     a.rho_inf = c->d_rhoinf;
     a.lam = c->d_lam;
-    a.begin = c->g.off[l];
+    a.begin = c->lay.soff[l];
     a.count = cnt;
     a.ph = phys(c, l);
     a.counters = c->d_counters;
@@ -279,7 +298,7 @@ void launch_collide(lbm_ctx *c, int l) {
       hipEventRecord(slot.b, c->stream);
       c->slots.push_back(slot);
     }
-    c->updates[l] += cnt;
+    c->updates[l] += c->g.off[l + 1] - c->g.off[l];
   }
   c->parity[l] ^= 1;
   c->pre[l] = false;
@@ -330,11 +349,12 @@ MArgs gather_args(lbm_ctx *c, int l, int mode) {
   a.gin = gbuf(c, l);
   a.lam = c->d_lam;
   a.stride = c->stride;
-  a.vbase = c->N;
-  a.nbr = c->d_nbr;
+  a.vbase = c->NS;
+  a.topo = topo(c);
   a.flags = c->d_flags;
-  a.begin = c->g.off[l];
-  a.count = c->g.off[l + 1] - c->g.off[l];
+  a.cell_of = c->d_cell_of;
+  a.begin = c->lay.soff[l];
+  a.count = c->lay.soff[l + 1] - c->lay.soff[l];
   PhysArgs ph = phys(c, l);
   a.cs2w = ph.cs2w;
   memcpy(a.uw, ph.uw, sizeof a.uw);
@@ -484,12 +504,41 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
     c->tau[l] = c->p.nu_finest <= 0.0 ? 0.5 : c->p.nu_finest / std::ldexp(1.0, n_levels - 1 - l) / cs2e + 0.5;
   c->N = c->g.n;
   c->Ng = c->g.goff[n_levels];
-  c->stride = ((c->N + c->Ng + 63) / 64) * 64;
+  {
+    bool periodic[3];
+    for (int a = 0; a < 3; ++a)
+      periodic[a] = a < dim && faces[2 * a].kind == LBM_BC_PERIODIC && faces[2 * a + 1].kind == LBM_BC_PERIODIC;
+    if (build_layout(c->g, c->lat, periodic, &c->lay, &err) != 0) return set_err(c, LBM_E_ARG, err);
+  }
+  c->NS = c->lay.nslot;
+  c->stride = ((c->NS + c->Ng + 63) / 64) * 64;
+  {
+    // bytes one update of level l must move at least: its populations in
+    // and out (and multipliers), plus the level's share of the flag, brick
+    // and exception tables and of the sponge fields
+    const int Q = c->lat.Q;
+    const double pops = 2.0 * Q * c->ops.sizeof_storage * (c->ddf ? 2 : 1) + (c->lamf ? 2.0 * NLAM * 4 : 0.0);
+    for (int l = 0; l < n_levels; ++l) {
+      const int64_t ncell = c->g.off[l + 1] - c->g.off[l];
+      const int64_t nsl = c->lay.soff[l + 1] - c->lay.soff[l];
+      int64_t nx = 0, nsp = 0;
+      for (int64_t k = c->g.off[l]; k < c->g.off[l + 1]; ++k) {
+        nx += c->lay.xrow_of[k] >= 0;
+        nsp += (c->g.flag[k] & F_SPONGE) != 0;
+      }
+      const double tables = nsl * (1.0 + (c->lay.nbp * 4.0 + 12.0) / 64.0) + nx * 4.0 * (Q - 1) + nsp * 16.0;
+      c->bpu[l] = ncell > 0 ? pops + tables / (double)ncell : pops;
+    }
+  }
   c->have_grid = true;
   if (c->p.host_only) return LBM_OK;
   // ---- device upload ----------------------------------------------------
   const int Q = c->lat.Q, Qm = Q - 1, NCH = 1 << dim;
   const size_t ssz = (size_t)c->ops.sizeof_storage;
+  const DeviceLayout &y = c->lay;
+  const int64_t N = c->N, NS = c->NS;
+  // bulk gathers address a population array with 32-bit byte offsets
+  if ((double)NS * (double)ssz >= 4294967296.0) return set_err(c, LBM_E_ARG, "grid too large for 32-bit offsets");
   for (int b = 0; b < 2; ++b) {
     c->f[b] = dev_alloc(c, ssz * Q * c->stride);
     if (!c->f[b]) return set_err(c, LBM_E_NOMEM, "population allocation failed");
@@ -498,58 +547,64 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
       if (!c->gb[b]) return set_err(c, LBM_E_NOMEM, "population allocation failed");
     }
   }
-  // internal neighbour encoding: coalesced slot for unknown coarse-ghost
-  // populations, the cell itself where the own value is kept, -1 for
-  // bounce-back, -2-k for the moving wall of face k
-  std::vector<int32_t> gidx(c->N, -1);
-  for (int64_t k = 0; k < c->Ng; ++k) gidx[c->g.ghost_cell[k]] = (int32_t)k;
-  c->d_nbr = (int32_t *)dev_alloc(c, sizeof(int32_t) * (size_t)Qm * c->stride);
-  if (!c->d_nbr) return set_err(c, LBM_E_NOMEM, "neighbour allocation failed");
-  {
-    std::vector<int32_t> row(c->N);
-    for (int i = 0; i < Qm; ++i) {
-      const int32_t *src = c->g.nbr.data() + (size_t)i * c->N;
-      const int64_t N = c->N;
-#pragma omp parallel for schedule(static)
-      for (int64_t cc = 0; cc < N; ++cc) {
-        const int32_t v = src[cc];
-        int32_t o;
-        if (v >= 0) o = v;
-        else if (v == NBR_NONE) o = gidx[cc] >= 0 ? (int32_t)(N + gidx[cc]) : (int32_t)cc;
-        else if (v == NBR_SOLID) o = -1;
-        else o = -2 - (-3 - v);
-        row[cc] = o;
-      }
-      HIP_TRY(c, hipMemcpy(c->d_nbr + (size_t)i * c->stride, row.data(), sizeof(int32_t) * N,
-                           hipMemcpyHostToDevice));
-    }
-  }
   lbm_status s;
+  if ((s = upload(c, &c->d_nbrick, y.nbrick.data(), y.nbrick.size())) != LBM_OK) return s;
+  if ((s = upload(c, &c->d_xmask, y.xmask.data(), y.xmask.size())) != LBM_OK) return s;
+  if ((s = upload(c, &c->d_xbase, y.xbase.data(), y.xbase.size())) != LBM_OK) return s;
+  if ((s = upload(c, &c->d_xnbr, y.xnbr.data(), y.xnbr.size())) != LBM_OK) return s;
+  if ((s = upload(c, &c->d_cell_of, y.cell_of.data(), y.cell_of.size())) != LBM_OK) return s;
+  if ((s = upload(c, &c->d_slot_of, y.slot_of.data(), y.slot_of.size())) != LBM_OK) return s;
   {
-    // device flags: the canonical ones plus F_MOVING where a population is
-    // pulled from a moving wall
-    std::vector<uint8_t> fl(c->g.flag);
-    const int64_t N = c->N;
+    // device flags per slot: the canonical ones, F_MOVING where a population
+    // is pulled from a moving wall, F_HOLE for slots without a cell
+    std::vector<uint8_t> fl(NS, (uint8_t)F_HOLE);
 #pragma omp parallel for schedule(static)
-    for (int64_t cc = 0; cc < N; ++cc)
+    for (int64_t cc = 0; cc < N; ++cc) {
+      uint8_t v = c->g.flag[cc];
       for (int i = 0; i < Qm; ++i)
-        if (c->g.nbr[(size_t)i * N + cc] <= -3) fl[cc] |= F_MOVING;
-    if ((s = upload(c, &c->d_flags, fl.data(), c->N)) != LBM_OK) return s;
+        if (c->g.nbr[(size_t)i * N + cc] <= -3) v |= F_MOVING;
+      fl[y.slot_of[cc]] = v;
+    }
+    if ((s = upload(c, &c->d_flags, fl.data(), fl.size())) != LBM_OK) return s;
   }
   if (!c->g.sigma.empty()) {
-    if ((s = upload(c, &c->d_sigma, c->g.sigma.data(), c->N)) != LBM_OK) return s;
-    if ((s = upload(c, &c->d_rhoinf, c->g.rho_inf.data(), c->N)) != LBM_OK) return s;
+    std::vector<double> sg(NS, 0.0), ri(NS, 0.0);
+    for (int64_t cc = 0; cc < N; ++cc) {
+      sg[y.slot_of[cc]] = c->g.sigma[cc];
+      ri[y.slot_of[cc]] = c->g.rho_inf[cc];
+    }
+    if ((s = upload(c, &c->d_sigma, sg.data(), sg.size())) != LBM_OK) return s;
+    if ((s = upload(c, &c->d_rhoinf, ri.data(), ri.size())) != LBM_OK) return s;
   }
   if (c->lamf) {
     c->d_lam = (float *)dev_alloc(c, sizeof(float) * NLAM * c->stride);
     if (!c->d_lam) return set_err(c, LBM_E_NOMEM, "multiplier allocation failed");
   }
-  if ((s = upload(c, &c->d_ghost, c->g.ghost_cell.data(), c->Ng)) != LBM_OK) return s;
-  if ((s = upload(c, &c->d_child, c->g.child.data(), (size_t)c->Ng * NCH)) != LBM_OK) return s;
+  {
+    // ghost, child and boundary lists over slots; every child of a coarse
+    // ghost has an exception row, which the coalescence pulls through
+    std::vector<int32_t> gs(c->g.ghost_cell.size()), ch(c->g.child.size()), cr(c->g.child.size(), 0);
+    for (size_t k = 0; k < gs.size(); ++k) gs[k] = y.slot_of[c->g.ghost_cell[k]];
+    for (size_t k = 0; k < ch.size(); ++k) {
+      const int32_t v = c->g.child[k];
+      ch[k] = v < 0 ? -1 : y.slot_of[v];
+      if (v >= 0) {
+        cr[k] = y.xrow_of[v];
+        if (cr[k] < 0) return set_err(c, LBM_E_ARG, "internal: child of a coarse ghost without an exception row");
+      }
+    }
+    std::vector<int32_t> bcc(c->g.bc_cell.size()), bcs(c->g.bc_src.size());
+    for (size_t k = 0; k < bcc.size(); ++k) bcc[k] = y.slot_of[c->g.bc_cell[k]];
+    for (size_t k = 0; k < bcs.size(); ++k) bcs[k] = y.slot_of[c->g.bc_src[k]];
+    if ((s = upload(c, &c->d_ghost, gs.data(), gs.size())) != LBM_OK) return s;
+    if ((s = upload(c, &c->d_child, ch.data(), ch.size())) != LBM_OK) return s;
+    if ((s = upload(c, &c->d_crow, cr.data(), cr.size())) != LBM_OK) return s;
+    if ((s = upload(c, &c->d_bc_cell, bcc.data(), bcc.size())) != LBM_OK) return s;
+    if ((s = upload(c, &c->d_bc_src, bcs.data(), bcs.size())) != LBM_OK) return s;
+  }
   if ((s = upload(c, &c->d_unknown, c->g.unknown.data(), c->Ng)) != LBM_OK) return s;
-  if ((s = upload(c, &c->d_bc_cell, c->g.bc_cell.data(), c->g.bc_cell.size())) != LBM_OK) return s;
-  if ((s = upload(c, &c->d_bc_src, c->g.bc_src.data(), c->g.bc_src.size())) != LBM_OK) return s;
   if ((s = upload(c, &c->d_bc_face, c->g.bc_face.data(), c->g.bc_face.size())) != LBM_OK) return s;
+  (void)NCH;
   c->d_counters = (unsigned long long *)dev_alloc(c, sizeof(unsigned long long) * CNT_COUNT);
   if (!c->d_counters) return set_err(c, LBM_E_NOMEM, "counter allocation failed");
   HIP_TRY(c, hipMemset(c->d_counters, 0, sizeof(unsigned long long) * CNT_COUNT));
@@ -569,6 +624,23 @@ lbm_status lbm_grid_info(lbm_ctx *c, int64_t *n_cells, int64_t *n_per_level, int
     e += (double)k / std::ldexp(1.0, c->L - 1 - l);
   }
   if (eq_fine) *eq_fine = e;
+  return LBM_OK;
+}
+
+lbm_status lbm_layout_info(lbm_ctx *c, int64_t *n_slots, int64_t *n_rows, int64_t *slots_per_level,
+                           int64_t *rows_per_level) {
+  if (!c) return LBM_E_ARG;
+  if (!c->have_grid) return set_err(c, LBM_E_STATE, "no grid");
+  if (n_slots) *n_slots = c->lay.nslot;
+  if (n_rows) *n_rows = c->lay.nx;
+  for (int l = 0; l < c->L; ++l) {
+    if (slots_per_level) slots_per_level[l] = c->lay.soff[l + 1] - c->lay.soff[l];
+    if (rows_per_level) {
+      int64_t k = 0;
+      for (int64_t q = c->g.off[l]; q < c->g.off[l + 1]; ++q) k += c->lay.xrow_of[q] >= 0;
+      rows_per_level[l] = k;
+    }
+  }
   return LBM_OK;
 }
 
@@ -618,6 +690,7 @@ static lbm_status init_common(lbm_ctx *c, const double *src, const double *src_g
   a.lam = c->d_lam;
   a.stride = c->stride;
   a.n = n;
+  a.slot_of = c->d_slot_of;
   a.src = d;
   a.src_g = dg;
   a.src_lam = dl;
@@ -737,7 +810,7 @@ lbm_status lbm_stats_get(lbm_ctx *c, lbm_stats *out) {
   memset(out, 0, sizeof *out);
   std::vector<int64_t> blocks(c->L), boff(c->L + 1, 0);
   for (int l = 0; l < c->L; ++l) {
-    blocks[l] = (c->g.off[l + 1] - c->g.off[l] + 255) / 256;
+    blocks[l] = (c->lay.soff[l + 1] - c->lay.soff[l] + 255) / 256;
     boff[l + 1] = boff[l] + blocks[l];
   }
   double *d = scratch(c, sizeof(double) * 6 * std::max<int64_t>(boff[c->L], 1));
@@ -990,13 +1063,7 @@ lbm_status lbm_profile_read(lbm_ctx *c, int level, int64_t *launches, double *to
   }
   if (launches) *launches = c->prof_launches[level];
   if (total_ms) *total_ms = c->prof_ms[level];
-  if (bytes_per_update) {
-    const int Q = c->lat.Q;
-    const double s = c->ops.sizeof_storage;
-    double b = 2.0 * Q * s * (c->ddf ? 2 : 1) + 4.0 * (Q - 1);
-    if (c->lamf) b += 2.0 * NLAM * sizeof(float);
-    *bytes_per_update = b;
-  }
+  if (bytes_per_update) *bytes_per_update = c->bpu[level];
   return LBM_OK;
 }
 

@@ -35,7 +35,18 @@ struct PhysArgs {
   const void *mlp;     // MLP operand block (device), or null
 };
 
-// collide-and-stream of the cells [begin, begin + count) of one level
+// pull topology of the slots: bricks of 64 slots with their neighbour
+// bricks, and explicit rows for the cells the brick arithmetic does not give
+struct Topo {
+  const int32_t *nbrick;   // [bricks][row] neighbour brick ids (slot / 64)
+  const uint64_t *xmask;   // [bricks] lanes with an exception row
+  const int32_t *xbase;    // [bricks] first exception row of the brick
+  const int32_t *xnbr;     // [Q-1][xstride] pull sources of the exception rows
+  int64_t xstride;
+};
+
+// collide-and-stream of the slots [begin, begin + count) of one level
+// (begin and count are multiples of 64)
 struct KArgs {
   const void *fin;
   void *fout;
@@ -43,7 +54,7 @@ struct KArgs {
   void *gout;
   int64_t stride;      // elements between two populations (SoA)
   int64_t vbase;       // first virtual (coalesced) slot
-  const int32_t *nbr;  // internal pull sources, SoA [Q-1][stride]
+  Topo topo;
   const uint8_t *flags;
   const double *sigma, *rho_inf; // sponge (may be null)
   float *lam;          // multipliers [8][stride] (DDF_NEWTON family)
@@ -60,8 +71,10 @@ struct CArgs {
   void *gout_coarse;
   float *lam;
   int64_t stride, vbase;
-  const int32_t *nbr;
-  const int32_t *child;     // [ghost][2^D]
+  const int32_t *xnbr;      // exception rows (children of coarse ghosts have one)
+  int64_t xstride;
+  const int32_t *child;     // [ghost][2^D] child slots
+  const int32_t *crow;      // [ghost][2^D] exception rows of the children
   const uint64_t *unknown;  // [ghost]
   const int32_t *ghost_cell;
   int64_t g0, count;        // ghosts [g0, g0 + count)
@@ -100,9 +113,10 @@ struct MArgs {
   const void *gin;
   const float *lam;
   int64_t stride, vbase;
-  const int32_t *nbr;
+  Topo topo;
   const uint8_t *flags;
-  int64_t begin, count;
+  const int32_t *cell_of;  // [slot] canonical cell, -1 for holes
+  int64_t begin, count;    // slots
   double cs2w, uw[6][3], Cv;
   int mode;            // 0: moments, 1: populations (+ multipliers), 2: sums
   double *out;         // moments [n_mom][n] / populations [Q][n] (g after)
@@ -118,6 +132,7 @@ struct IArgs {
   void *g;
   float *lam;
   int64_t stride, n;
+  const int32_t *slot_of;  // [n] slot of a canonical cell
   const double *src;   // moments [n_mom][n] or populations [Q][n]
   const double *src_g, *src_lam;
   int mode;            // 0: equilibrium from moments, 1: raw populations

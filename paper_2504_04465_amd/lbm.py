@@ -25,7 +25,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_MASK", -3: "LBM_E_NOMEM", -4:
           -5: "LBM_E_STATE", -6: "LBM_E_NUMERIC", -7: "LBM_E_UNSUPPORTED"}
 
 # every entry point declared in include/lbm.h
-EXPORTS = ["lbm_create", "lbm_grid_build", "lbm_grid_info", "lbm_grid_export", "lbm_init",
+EXPORTS = ["lbm_create", "lbm_grid_build", "lbm_grid_info", "lbm_layout_info", "lbm_grid_export", "lbm_init",
            "lbm_step", "lbm_set_face_bc", "lbm_moments", "lbm_moments_device", "lbm_stats_get",
            "lbm_sync", "lbm_profile_enable", "lbm_profile_read", "lbm_get_state", "lbm_set_state",
            "lbm_last_error", "lbm_destroy", "lbm_mlp_set_weights", "lbm_mlp_get_weights",
@@ -84,6 +84,7 @@ def lib():
         L.lbm_create.argtypes = [C.POINTER(Params), ALLOC_FN, FREE_FN, vp, vp, C.POINTER(vp)]
         L.lbm_grid_build.argtypes = [vp, C.c_int, vp, C.c_int, vp, vp, vp]
         L.lbm_grid_info.argtypes = [vp, vp, vp, vp, vp]
+        L.lbm_layout_info.argtypes = [vp, vp, vp, vp, vp]
         L.lbm_grid_export.argtypes = [vp] + [vp] * 6
         L.lbm_init.argtypes = [vp, vp]
         L.lbm_step.argtypes = [vp, i64]
@@ -256,6 +257,17 @@ class LBM:
         self.n, self.n_per_level, self.n_ghosts, self.eq_fine = n.value, npl[:n_levels].copy(), ng.value, eq.value
         self.Q = {"D2Q9": 9, "D3Q27": 27, "D2Q21": 21, "D2Q37": 37}[self.lattice]
         self.n_mom = 1 + dim + (1 if self.ddf else 0)
+
+    def layout(self):
+        """device placement: total slots, cells with explicit pull rows, and
+        both per level"""
+        ns, nx = C.c_int64(), C.c_int64()
+        spl = np.zeros(8, np.int64)
+        rpl = np.zeros(8, np.int64)
+        self._check(self._L.lbm_layout_info(self.h, C.byref(ns), C.byref(nx), _ptr(spl), _ptr(rpl)),
+                    "lbm_layout_info")
+        return dict(slots=ns.value, exception_rows=nx.value, slots_per_level=spl[: self.n_levels].tolist(),
+                    rows_per_level=rpl[: self.n_levels].tolist())
 
     def export(self):
         n, Q = self.n, self.Q

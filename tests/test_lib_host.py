@@ -110,3 +110,34 @@ def test_equivalent_fine_cells_paper_table():
         coarse_first = nums[::-1]  # library numbering: level 0 coarsest
         assert sum(nums) == int(total)
         assert int(B.equivalent_fine_cells(coarse_first)) == int(eq)
+
+
+@pytest.mark.parametrize("name,w", cases(), ids=[c[0] for c in cases()])
+def test_brick_layout_counts(name, w):
+    """Device placement: slots come in whole 64-slot bricks per level, every
+    cell has one, and every ghost / boundary-layer cell keeps an explicit
+    row of pull sources (the brick arithmetic covers bulk cells only)."""
+    s = B.LBM.from_workload(w, host_only=True)
+    lay = s.layout()
+    assert lay["slots"] % 64 == 0 and sum(lay["slots_per_level"]) == lay["slots"]
+    assert all(v % 64 == 0 for v in lay["slots_per_level"])
+    assert all(sl >= n for sl, n in zip(lay["slots_per_level"], s.n_per_level))
+    e = s.export()
+    lev, flags = e["level"], e["flags"]
+    special = (flags & 0x0F) != 0  # coarse ghost, fine ghost, Neumann, equilibrium layer
+    for l in range(s.n_levels):
+        assert lay["rows_per_level"][l] >= int(np.count_nonzero(special & (lev == l)))
+        assert lay["rows_per_level"][l] <= int(s.n_per_level[l])
+
+
+def test_brick_layout_uniform_periodic_needs_no_rows():
+    """On a periodic uniform grid whose extent is a whole number of bricks
+    every cell is a bulk cell; with an extent that is not, only cells within
+    the lattice reach of the wrap need rows."""
+    s = B.LBM.from_workload(W.shear(n=32, levels=1, steps=1), host_only=True)
+    assert s.layout()["exception_rows"] == 0
+    s = B.LBM.from_workload(W.shear(n=20, levels=1, steps=1), host_only=True)
+    rows = s.layout()["exception_rows"]
+    # wrap columns / rows: the last brick is half empty, so cells within one
+    # cell of the wrap in x or y take rows: 20 * 20 - 18 * 18 = 76
+    assert rows == 20 * 20 - 18 * 18
