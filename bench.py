@@ -83,6 +83,167 @@ def cpu_baseline_child(args):
                                 f"{dt:.1f} s"}))
 
 
+KERNEL_SOURCES = ["kernels.cuh", "k_d3q27.hip", "lattice.h", "ops.h", "layout.h", "layout.cpp",
+                  "grid_builder.h", "grid_builder.cpp"]
+
+
+def counted_traffic(workload_name, storage):
+    """HBM bytes per update of the collide kernel per level, measured with
+    rocprofv3 counters and stored in the profile of this kernel and workload;
+    None when there is no profile or the kernel's sources changed since."""
+    import hashlib
+    if workload_name != "sphere" or storage != "fp32":
+        return None
+    prof = os.path.join(ROOT, "profiles", "k_collide_d3q27_rr_fp32_sphere.md")
+    if not os.path.exists(prof):
+        return None
+    rec = None
+    for line in open(prof):
+        line = line.strip()
+        if line.startswith("traffic {"):
+            rec = json.loads(line[len("traffic "):])
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2504_04465_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return {int(k): v for k, v in rec["bytes_per_update"].items()}
+
+
+def rel_l2(a, b, vol):
+    """volume-weighted relative L2 of a against b over the cells where both
+    are finite (fine ghosts are NaN)"""
+    import numpy as np
+    vol = np.broadcast_to(vol, a.shape)
+    ok = np.isfinite(a) & np.isfinite(b)
+    den = np.sqrt(np.sum(vol[ok] * b[ok] ** 2))
+    return float(np.sqrt(np.sum(vol[ok] * (a[ok] - b[ok]) ** 2)) / den) if den > 0 else 0.0
+
+
+def surrogate_leg(args):
+    """D2Q21 numerical-equilibrium step (supersonic airfoil) with the Newton
+    solve, cold and warm started, against the multiplier surrogate alone and
+    with one Newton correction plus Newton fallback.  All variants start from
+    the same developed flow; errors are against the FP64-storage Newton path
+    from the same state (the GPU path the parity tests tie to the oracle)."""
+    import numpy as np
+    import torch
+    from paper_2504_04465_amd import lbm as B
+    from paper_2504_04465_amd import workloads as W
+    K, dev = args.sur_steps, args.sur_develop
+    w = W.airfoil(scale=args.sur_scale, steps=dev + K + 2)
+    t_all = time.perf_counter()
+
+    def ctx(coll, sto, warm):
+        c = B.LBM(w.lattice, coll, sto, nu_finest=w.nu_finest, T0=w.T0, gamma=w.gamma, sensor_A=w.sensor_A,
+                  sensor_on=w.sensor_on, newton_tol=w.newton_tol, newton_max_it=w.newton_max_it, warm_start=warm)
+        c.grid(w.dim, w.ext, w.n_levels, w.refine, w.solid, w.faces)
+        return c
+
+    def faces(c, k):
+        for face, f in w.schedule(k).items():
+            c.set_face(face, f)
+
+    # training set: Newton labels of seeded states from the training box
+    lab = ctx("DDF_NEWTON", "fp32", True)
+    x = W.mlp_samples(args.sur_samples, seed=5)
+    t0 = time.perf_counter()
+    lam, ok, _ = lab.mlp_label(x)
+    t1 = time.perf_counter()
+    hist = lab.mlp_train(x[ok], lam[ok], epochs=args.sur_epochs, batch=1024, lr=1e-2, seed=5)
+    t2 = time.perf_counter()
+    wts = lab.mlp_get_weights()
+    lab.close()
+    # developed flow
+    d = ctx("DDF_NEWTON", "fp32", True)
+    d.init_workload(w)
+    for k in range(dev):
+        faces(d, k)
+        d.step(1)
+    d.sync()
+    state = d.get_state()
+    _, level = d.coords_levels()
+    vol = np.ldexp(1.0, -2 * level.astype(np.int64))
+    n_cells = d.n
+    d.close()
+
+    def run(coll, sto, warm):
+        c = ctx(coll, sto, warm)
+        if coll != "DDF_NEWTON":
+            c.mlp_set_weights(wts)
+        c.set_state(*state)
+        for k in range(dev, dev + 2):
+            faces(c, k)
+            c.step(1)
+        c.sync()
+        s0 = c.stats()
+        torch.cuda.synchronize()
+        c.profile(True)
+        ta = time.perf_counter()
+        for k in range(dev + 2, dev + 2 + K):
+            faces(c, k)
+            c.step(1)
+        c.sync()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - ta) * 1e3
+        coll_ms = sum(c.profile_read(l)[1] for l in range(w.n_levels))
+        s1 = c.stats()
+        m = c.moments()
+        c.close()
+        upd = sum(s1["updates"]) - sum(s0["updates"])
+        it = s1["newton_iterations"] - s0["newton_iterations"]
+        fb = s1["mlp_fallbacks"] - s0["mlp_fallbacks"]
+        return {"step_ms": round(wall / K, 3), "collide_ms": round(coll_ms / K, 3),
+                "newton_it_per_update": round(it / max(upd, 1), 3),
+                "fallback_rate": round(fb / max(upd, 1), 4)}, m
+
+    ref_stats, ref = run("DDF_NEWTON", "fp64", True)
+    out = {"workload": f"airfoil D2Q21 numerical equilibrium, {w.ext[0]}x{w.ext[1]} coarse, {w.n_levels} levels, "
+                       f"{n_cells} cells, fp32 populations, FP64 Newton",
+           "developed_coarse_steps": dev, "timed_coarse_steps": K,
+           "training": {"samples_drawn": int(len(x)), "accepted": int(ok.sum()), "epochs": args.sur_epochs,
+                        "label_s": round(t1 - t0, 3), "train_s": round(t2 - t1, 3),
+                        "loss_first_last": [float(hist[0]), float(hist[-1])]},
+           "reference": dict(ref_stats, storage="fp64", warm_start=True)}
+    for name, coll, warm in [("a_cold", "DDF_NEWTON", False), ("a_warm", "DDF_NEWTON", True),
+                             ("b_mlp", "DDF_MLP", True), ("c_mlp_newton", "DDF_MLP_NEWTON", True)]:
+        try:
+            st, m = run(coll, "fp32", warm)
+            st["rel_l2_vs_fp64"] = {"rho": rel_l2(m[0], ref[0], vol), "u": rel_l2(m[1:3], ref[1:3], vol[None, :]),
+                                    "T": rel_l2(m[3], ref[3], vol)}
+        except B.LbmError as e:
+            st = {"failed": str(e)[:160]}
+        out[name] = st
+        print(f"[bench] surrogate {name}: {st}", file=sys.stderr, flush=True)
+    c = out["c_mlp_newton"]
+    if "step_ms" in c:
+        out["speedup_c_vs_a_cold"] = {"step": round(out["a_cold"]["step_ms"] / c["step_ms"], 3),
+                                      "collide": round(out["a_cold"]["collide_ms"] / c["collide_ms"], 3)}
+        out["speedup_c_vs_a_warm"] = {"step": round(out["a_warm"]["step_ms"] / c["step_ms"], 3),
+                                      "collide": round(out["a_warm"]["collide_ms"] / c["collide_ms"], 3)}
+    out["seconds"] = round(time.perf_counter() - t_all, 1)
+    return out
+
+
+def calibrate_copy():
+    """A plain copy of exactly 1 GiB (read 1 GiB, write 1 GiB) on the device:
+    under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE it gives the factor between
+    the counters and the bytes moved."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)  # device-to-device copy
+    torch.cuda.synchronize()
+    torch.mul(a, 2.0, out=b)  # elementwise kernel: read 1 GiB, write 1 GiB
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": 4 * n, "ok": bool(b[-1].item() == 2.0)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,10 +255,21 @@ def main():
     ap.add_argument("--cpu-scale", type=int, default=4)
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--sur-scale", type=int, default=1)
+    ap.add_argument("--sur-steps", type=int, default=8)
+    ap.add_argument("--sur-develop", type=int, default=100)
+    ap.add_argument("--sur-samples", type=int, default=3_300_000)
+    ap.add_argument("--sur-epochs", type=int, default=40)
     ap.add_argument("--cpu-baseline-child", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="one plain 1 GiB device-to-device copy, to scale the HBM byte counters")
     args = ap.parse_args()
     if args.cpu_baseline_child:
         cpu_baseline_child(args)
+        return
+    if args.calibrate_copy:
+        calibrate_copy()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -154,6 +326,13 @@ def main():
         launches += n_l
     achieved = tot_bytes / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
     _, _, bpu_f = s.profile_read(L - 1)
+    # counter-measured HBM bytes of the same launches, at the same rate basis
+    counted = counted_traffic(w.name, storage)
+    traffic = traffic_bpu = None
+    if counted is not None and tot_ms > 0:
+        tb = sum(counted[l] * int(s.n_per_level[l]) * s.profile_read(l)[0] for l in range(L))
+        traffic = round(tb / (tot_ms * 1e-3) / 1e9, 1)
+        traffic_bpu = round(tb / sum(int(s.n_per_level[l]) * s.profile_read(l)[0] for l in range(L)), 1)
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -172,15 +351,20 @@ def main():
                    "updates_per_coarse_step": per_step,
                    "equivalent_fine_cells": s.eq_fine},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_collide", "launches": launches,
                      "avg_launch_ms": round(tot_ms / max(launches, 1), 5),
-                     "bytes_per_update": bpu_f},
+                     "bytes_per_update": round(tot_bytes / max(sum(int(s.n_per_level[l]) * s.profile_read(l)[0]
+                                                                  for l in range(L)), 1), 2),
+                     "traffic_bytes_per_update": traffic_bpu},
         "modeled_hbm_frac_whole_step": round(per_step * bpu_f * args.steps / dt / 1e9 / HBM_PEAK_GBS, 4),
         "mlups_paper_formula": round(s.n * args.steps * (1 << (L - 1)) / dt / 1e6, 2),
         "newton": {"calls": st["newton_calls"], "iterations": st["newton_iterations"],
                    "failures": st["newton_failures"]},
     }
+    s.close()
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)
