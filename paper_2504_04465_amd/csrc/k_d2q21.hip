@@ -57,36 +57,34 @@ __global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
       rhop = rho * ((C)1 - s) + s * (C)a.rho_inf[c];
     }
     if (!(rho > (C)0) || !isfinite(rho)) count_add(a.counters, CNT_NONFINITE, 1);
-    double e[Q], M[NLAM], G[NLAM];
-    targets<L>((double)u[0], (double)u[1], (double)T, M);
-    expo_residual<L>(lam, M, e, G);
+    C e[Q];
     if constexpr (COLL == COLL_DDF_MLP_NEWTON) {
-      const bool ok = newton_step<L>(lam, G, e, M);
-      if (!ok || !(nrmmax_8(G) <= a.ph.fallback_tol)) {
-        // full Newton, continued from the corrected multipliers
-        count_add(a.counters, CNT_MLP_FALLBACK, 1);
-        count_add(a.counters, CNT_NEWTON_CALLS, 1);
-        int it = 0;
-        bool good = ok;
-        if (!ok) {
+      // one Newton correction from the network's multipliers; where the
+      // residual then exceeds fallback_tol, Newton continues from the
+      // corrected multipliers to newton_tol (from zero if the correction
+      // itself failed)
+      count_add(a.counters, CNT_NEWTON_CALLS, 1);
+      int it = newton_lean<L, C>((double)u[0], (double)u[1], (double)T, lam, a.ph.newton_tol, a.ph.newton_max_it, 1,
+                                 a.ph.fallback_tol, e);
+      if (it != 1) count_add(a.counters, CNT_MLP_FALLBACK, 1);
+      if (it < 0) {
 #pragma unroll
-          for (int k = 0; k < NLAM; ++k) lam[k] = 0.0;
-          expo_residual<L>(lam, M, e, G);
-          good = true;
-        }
-        while (good && !(nrmmax_8(G) <= a.ph.newton_tol) && it < a.ph.newton_max_it) {
-          good = newton_step<L>(lam, G, e, M);
-          ++it;
-        }
-        if (!good || !(nrmmax_8(G) <= a.ph.newton_tol)) count_add(a.counters, CNT_NEWTON_FAIL, 1);
-        else count_add(a.counters, CNT_NEWTON_ITERS, (unsigned long long)it);
+        for (int k = 0; k < NLAM; ++k) lam[k] = 0.0;
+        it = newton_lean<L, C>((double)u[0], (double)u[1], (double)T, lam, a.ph.newton_tol, a.ph.newton_max_it, 0,
+                               a.ph.newton_tol, e);
       }
+      if (it < 0) count_add(a.counters, CNT_NEWTON_FAIL, 1);
+      else count_add(a.counters, CNT_NEWTON_ITERS, (unsigned long long)it);
+    } else {
+      // the network's multipliers as they are
+      double G[NLAM];
+      expo_pass<L, C, false>(lam, (double)u[0], (double)u[1], (double)T, G, nullptr, e);
     }
     C feq[Q], geq[Q];
     const C kg = ((C)2 * (C)a.ph.Cv - (C)L::D) * T;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      feq[i] = (C)((double)rhop * e[i]);
+      feq[i] = rhop * e[i];
       geq[i] = kg * feq[i];
     }
     C te = (C)a.ph.tau;

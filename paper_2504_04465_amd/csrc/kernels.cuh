@@ -454,24 +454,44 @@ __device__ constexpr double mvec(int i, int a) {
        : a == 6 ? x * n2 : y * n2;
 }
 
+// One pass over the populations at multipliers lam (Eq. exponential):
+// e_i = exp(-(1 + lam . m_i)), the constraint residuals
+// G_a = sum_i e_i m_ia - M_a (Eqs. G0_8mom - G3yaa_8mom, per unit density)
+// and the Newton matrix H = sum_i e_i m_i m_i^T (packed lower triangle).
+// e_i is kept only in the collision precision C, for the final equilibrium,
+// so that no FP64 population array stays live across the solve.
 template <class L>
-__device__ inline void expo_residual(const double *lam, const double *M, double *e, double *G) {
+__device__ inline void targets(double ux, double uy, double T, double *M);
+
+template <class L, class C, bool HESS = true>
+__device__ inline void expo_pass(const double *lam, double ux, double uy, double T, double *G, double *H, C *e) {
+#pragma unroll
+  for (int a = 0; a < NLAM; ++a) G[a] = 0.0;
+  if (HESS)
+#pragma unroll
+    for (int k = 0; k < NLAM * (NLAM + 1) / 2; ++k) H[k] = 0.0;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
     double s = 1.0;
 #pragma unroll
     for (int a = 0; a < NLAM; ++a)
       if (mvec<L>(i, a) != 0.0) s += lam[a] * mvec<L>(i, a);
-    e[i] = exp(-s);
-  }
+    const double ei = exp(-s);
+    e[i] = (C)ei;
 #pragma unroll
-  for (int a = 0; a < NLAM; ++a) {
-    double acc = 0.0;
+    for (int a = 0; a < NLAM; ++a) {
+      if (mvec<L>(i, a) == 0.0) continue;
+      G[a] += ei * mvec<L>(i, a);
+      if (!HESS) continue;
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i)
-      if (mvec<L>(i, a) != 0.0) acc += e[i] * mvec<L>(i, a);
-    G[a] = acc - M[a];
+      for (int b = 0; b <= a; ++b)
+        if (mvec<L>(i, b) != 0.0) H[a * (a + 1) / 2 + b] += ei * (mvec<L>(i, a) * mvec<L>(i, b));
+    }
   }
+  double M[NLAM];
+  targets<L>(ux, uy, T, M);
+#pragma unroll
+  for (int a = 0; a < NLAM; ++a) G[a] -= M[a];
 }
 
 __device__ inline double nrm2_8(const double *G) {
@@ -505,31 +525,16 @@ __device__ inline void targets(double ux, double uy, double T, double *M) {
   M[7] = uy * (uu + 4.0 * T);
 }
 
-// one Newton step from (lam, G, e): solves (sum e m m^T) d = G by Cholesky
-// and backtracks; returns false if the matrix is not positive definite
-template <class L>
-__device__ inline bool newton_step(double *lam, double *G, double *e, const double *M) {
-  double H[NLAM * (NLAM + 1) / 2];
-#pragma unroll
-  for (int a = 0; a < NLAM; ++a)
-#pragma unroll
-    for (int b = 0; b <= a; ++b) {
-      double acc = 0.0;
-#pragma unroll
-      for (int i = 0; i < L::Q; ++i) {
-        const double mm = mvec<L>(i, a) * mvec<L>(i, b);
-        if (mm != 0.0) acc += e[i] * mm;
-      }
-      H[a * (a + 1) / 2 + b] = acc;
-    }
-  // in-place Cholesky, packed lower triangle
+// d = H^-1 G by an in-place Cholesky factorisation of the packed H; false
+// when H is not numerically positive definite
+__device__ inline bool cholesky_solve(double *H, const double *G, double *d) {
 #pragma unroll
   for (int j = 0; j < NLAM; ++j) {
-    double d = H[j * (j + 1) / 2 + j];
+    double t = H[j * (j + 1) / 2 + j];
 #pragma unroll
-    for (int k = 0; k < j; ++k) d -= H[j * (j + 1) / 2 + k] * H[j * (j + 1) / 2 + k];
-    if (!(d > 0.0)) return false;
-    const double ljj = sqrt(d);
+    for (int k = 0; k < j; ++k) t -= H[j * (j + 1) / 2 + k] * H[j * (j + 1) / 2 + k];
+    if (!(t > 0.0)) return false;
+    const double ljj = sqrt(t);
     H[j * (j + 1) / 2 + j] = ljj;
     const double inv = 1.0 / ljj;
 #pragma unroll
@@ -540,53 +545,72 @@ __device__ inline bool newton_step(double *lam, double *G, double *e, const doub
       H[i * (i + 1) / 2 + j] = s * inv;
     }
   }
-  double y[NLAM], dlt[NLAM];
 #pragma unroll
   for (int i = 0; i < NLAM; ++i) {
     double s = G[i];
 #pragma unroll
-    for (int k = 0; k < i; ++k) s -= H[i * (i + 1) / 2 + k] * y[k];
-    y[i] = s / H[i * (i + 1) / 2 + i];
+    for (int k = 0; k < i; ++k) s -= H[i * (i + 1) / 2 + k] * d[k];
+    d[i] = s / H[i * (i + 1) / 2 + i];
   }
 #pragma unroll
   for (int i = NLAM - 1; i >= 0; --i) {
-    double s = y[i];
+    double s = d[i];
 #pragma unroll
-    for (int k = i + 1; k < NLAM; ++k) s -= H[k * (k + 1) / 2 + i] * dlt[k];
-    dlt[i] = s / H[i * (i + 1) / 2 + i];
+    for (int k = i + 1; k < NLAM; ++k) s -= H[k * (k + 1) / 2 + i] * d[k];
+    d[i] = s / H[i * (i + 1) / 2 + i];
   }
-  const double n0 = nrm2_8(G);
-  double alpha = 1.0, trial[NLAM], Gt[NLAM], et[L::Q];
-  for (int h = 0; h <= 30; ++h) {
-#pragma unroll
-    for (int a = 0; a < NLAM; ++a) trial[a] = lam[a] + alpha * dlt[a];
-    expo_residual<L>(trial, M, et, Gt);
-    if (nrm2_8(Gt) < n0 || h == 30) break;
-    alpha *= 0.5;
-  }
-#pragma unroll
-  for (int a = 0; a < NLAM; ++a) {
-    lam[a] = trial[a];
-    G[a] = Gt[a];
-  }
-#pragma unroll
-  for (int i = 0; i < L::Q; ++i) e[i] = et[i];
   return true;
 }
 
-// returns the iteration count, or -1 when not converged
-template <class L>
-__device__ inline int newton_solve(double ux, double uy, double T, double *lam, double tol,
-                                   int max_it, double *e) {
-  double M[NLAM], G[NLAM];
-  targets<L>(ux, uy, T, M);
-  expo_residual<L>(lam, M, e, G);
-  for (int it = 0; it <= max_it; ++it) {
-    if (nrmmax_8(G) <= tol) return it;
-    if (it == max_it) break;
-    if (!newton_step<L>(lam, G, e, M)) return -1;
+// Newton-Raphson on the eight constraints from the multipliers in lam, with
+// backtracking on the 2-norm of the residual (at most 30 halvings).  The
+// stopping test max_a |G_a| <= tol is applied before every step; the first
+// min_steps steps are always taken, and after exactly min_steps steps the
+// looser tolerance tol_first applies (the surrogate's single correction).
+// Returns the number of steps, or -1 (not converged within max_it, or H not
+// positive definite).  e receives exp(-(1 + lam . m_i)) at the final lam.
+template <class L, class C>
+__device__ inline int newton_lean(double ux, double uy, double T, double *lam, double tol, int max_it,
+                                  int min_steps, double tol_first, C *e) {
+  double G[NLAM], H[NLAM * (NLAM + 1) / 2], d[NLAM], base[NLAM];
+  // one evaluation site: each pass either checks a new iterate or tests a
+  // trial point of the line search
+  int it = 0, h = 0;
+  bool trial = false;
+  double n0 = 0.0, alpha = 1.0;
+  for (;;) {
+    expo_pass<L, C>(lam, ux, uy, T, G, H, e);
+    if (trial) {
+      if (!(nrm2_8(G) < n0) && h < 30) {
+        ++h;
+        alpha *= 0.5;
+#pragma unroll
+        for (int a = 0; a < NLAM; ++a) lam[a] = base[a] + alpha * d[a];
+        continue;
+      }
+      trial = false;
+      ++it;
+    }
+    if (it >= min_steps && nrmmax_8(G) <= (it == min_steps && min_steps > 0 ? tol_first : tol)) return it;
+    if (it == max_it) return -1;
+    if (!cholesky_solve(H, G, d)) return -1;
+    n0 = nrm2_8(G);
+    alpha = 1.0;
+    h = 0;
+#pragma unroll
+    for (int a = 0; a < NLAM; ++a) {
+      base[a] = lam[a];
+      lam[a] = base[a] + alpha * d[a];
+    }
+    trial = true;
   }
-  return -1;
+}
+
+// cold-or-warm Newton solve to tol (the paper's solver); FP64 equilibrium out
+template <class L>
+__device__ inline int newton_solve(double ux, double uy, double T, double *lam, double tol, int max_it,
+                                   double *e) {
+  return newton_lean<L, double>(ux, uy, T, lam, tol, max_it, 0, tol, e);
 }
 
 // ---------------------------------------------------------------------------
@@ -645,10 +669,11 @@ __device__ inline int equilibrium_any(C rho, const C *u, C T, const PhysArgs &ph
     if (!warm)
 #pragma unroll
       for (int a = 0; a < NLAM; ++a) lam[a] = 0.0;
-    double e[L::Q];
-    it = newton_solve<L>((double)u[0], (double)u[1], (double)T, lam, ph.newton_tol, ph.newton_max_it, e);
+    C e[L::Q];
+    it = newton_lean<L, C>((double)u[0], (double)u[1], (double)T, lam, ph.newton_tol, ph.newton_max_it, 0,
+                           ph.newton_tol, e);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) feq[i] = (C)((double)rho * e[i]);
+    for (int i = 0; i < L::Q; ++i) feq[i] = rho * e[i];
   }
   if constexpr (COLL >= COLL_DDF_POLY) {
     const C k = ((C)2 * (C)ph.Cv - (C)L::D) * T;
@@ -672,7 +697,7 @@ __device__ inline void count_add(unsigned long long *ctr, int which, unsigned lo
 // choice.
 template <class L, int COLL, class S>
 struct MinWaves {
-  static constexpr int value = COLL < COLL_DDF_POLY ? (sizeof(S) == 8 ? 4 : 6) : 1;
+  static constexpr int value = COLL < COLL_DDF_POLY ? (sizeof(S) == 8 ? 4 : 6) : (COLL >= COLL_DDF_NEWTON ? 2 : 1);
 };
 
 template <class L, int COLL, class S, bool PRE>

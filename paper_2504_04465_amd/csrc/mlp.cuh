@@ -43,9 +43,12 @@ __device__ inline f32x16 mfma32(bf16x8 a, bf16x8 b, f32x16 c) {
 
 __device__ inline int c_row(int l, int r) { return ((r >> 2) << 3) + ((l >> 5) << 2) + (r & 3); }
 
-__device__ inline float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU and its derivative with the hardware exponential and reciprocal
+// (about 1 ulp each; the activations are rounded to BF16 right after)
+__device__ inline float sigmoid_f(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ inline float silu_f(float z) { return z * sigmoid_f(z); }
 __device__ inline float dsilu_f(float z) {
-  const float s = 1.0f / (1.0f + __expf(-z));
+  const float s = sigmoid_f(z);
   return s * (1.0f + z * (1.0f - s));
 }
 
