@@ -229,6 +229,15 @@ lbm_status lbm_get_state(lbm_ctx *ctx, double *f, double *g, double *lambda);
 lbm_status lbm_set_state(lbm_ctx *ctx, const double *f, const double *g,
                          const double *lambda);
 
+/* The state of the listed cells only (same content as lbm_get_state, at the
+ * synchronisation point of Sec. 4.5): cells [n] canonical indices; f [Q][n],
+ * g [Q][n] (DDF), lambda [8][n] (Newton family, may be NULL), host arrays
+ * owned by the caller, entry k for cells[k].  Lets a caller sample a large
+ * grid without copying all of it.  Errors: LBM_E_ARG (index out of range),
+ * LBM_E_STATE, LBM_E_DEVICE. */
+lbm_status lbm_get_cells(lbm_ctx *ctx, const int64_t *cells, int64_t n, double *f, double *g,
+                         double *lambda);
+
 /* ---- multiplier surrogate (D2Q21 contexts) ----------------------------
  * A small network replaces the per-cell Newton solve of the numerical
  * equilibrium (App. A.2, Eq. exponential, constraints G(0)..G(3)): it maps

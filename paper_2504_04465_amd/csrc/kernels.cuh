@@ -232,6 +232,42 @@ __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const 
   }
 }
 
+// Gather for one cell anywhere (no brick per wavefront): the neighbour
+// brick ids come straight from the table.  Used by the sampled read-back.
+template <class L, class S, bool PRE, bool DDF>
+__device__ inline void gather_one(const S *fin, const S *gin, const Topo &tp, int64_t stride, int64_t vbase,
+                                  int64_t c, const double (&uw)[6][3], double cs2w, typename Sto<S>::C *f,
+                                  typename Sto<S>::C *g) {
+  constexpr int BS = Brick<L>::BS;
+  const int64_t brick = c >> 6;
+  const int lane = (int)(c & 63);
+  const uint64_t xm = tp.xmask[brick];
+  if ((xm >> lane) & 1ull) {
+    gather<L, S, PRE, DDF>(fin, gin, tp, nullptr, stride, vbase, c, lane, (int32_t)brick, xm, uw, cs2w, f, g);
+    return;
+  }
+  f[0] = Sto<S>::ld(fin, c, L::S.w[0]);
+  if (DDF) g[0] = Sto<S>::ld(gin, c, 0.0);
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) {
+    int64_t src = c;
+    if (!PRE) {
+      int dir = 0, loc = 0, pw = 1;
+#pragma unroll
+      for (int d = 0; d < L::D; ++d) {
+        const int p = lane_coord<L>(lane, d) - cx_<L>(i, d);
+        const int w = p < 0 ? 0 : (p >= BS ? 2 : 1);
+        dir += w * pw;
+        pw *= 3;
+        loc |= lane_bits<L>(p & (BS - 1), d);
+      }
+      src = (int64_t)tp.nbrick[brick * Brick<L>::NBP + dir] * 64 + loc;
+    }
+    f[i] = Sto<S>::ld(fin, (int64_t)i * stride + src, L::S.w[i]);
+    if (DDF) g[i] = Sto<S>::ld(gin, (int64_t)i * stride + src, 0.0);
+  }
+}
+
 // Per-block preamble of the kernels that gather: stages the byte offsets of
 // the neighbour bricks of the block's four bricks in LDS.  Every thread of
 // the block must call it.  Returns the wave-uniform brick id.
@@ -946,6 +982,24 @@ __global__ void __launch_bounds__(BLOCK) k_gather(const MArgs a) {
   constexpr int Q = L::Q;
   __shared__ uint32_t nbs[BLOCK / 64][Brick<L>::NBP];
   const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (a.mode == 3) {
+    // populations (and multipliers) of the listed cells of this level
+    if (t >= a.count) return;
+    const int64_t k = a.list_begin + t;
+    const int32_t cell = a.cells_list[k];
+    const int64_t c = a.slot_of[cell];
+    C f[Q];
+    C g[DDF ? Q : 1];
+    gather_one<L, S, PRE, DDF>((const S *)a.fin, (const S *)a.gin, a.topo, a.stride, a.vbase, c, a.uw, a.cs2w, f, g);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      a.out[(int64_t)i * a.n + k] = (double)f[i];
+      if (DDF) a.out[(int64_t)(Q + i) * a.n + k] = (double)g[i];
+    }
+    if (a.lam_out)
+      for (int q = 0; q < NLAM; ++q) a.lam_out[(int64_t)q * a.n + k] = (double)a.lam[(int64_t)q * a.stride + c];
+    return;
+  }
   const bool live = t < a.count;  // whole wavefronts
   const int64_t c = a.begin + (live ? t : 0);
   const int32_t brick = stage_bricks<L, S>(a.topo, nbs, c, live);

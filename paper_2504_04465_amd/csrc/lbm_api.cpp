@@ -803,6 +803,66 @@ lbm_status lbm_get_state(lbm_ctx *c, double *f, double *g, double *lambda) {
   return LBM_OK;
 }
 
+lbm_status lbm_get_cells(lbm_ctx *c, const int64_t *cells, int64_t n, double *f, double *g, double *lambda) {
+  lbm_status s = need_state(c);
+  if (s != LBM_OK) return s;
+  if (n < 0 || (n > 0 && (!cells || !f || (c->ddf && !g)))) return set_err(c, LBM_E_ARG, "bad arguments");
+  if (n == 0) return LBM_OK;
+  const int Q = c->lat.Q;
+  // group the request by level (stable), keeping each entry's position
+  std::vector<int64_t> order(n);
+  std::vector<int32_t> lst(n);
+  std::vector<int64_t> lbeg(c->L + 1, 0);
+  std::vector<int> lev(n);
+  for (int64_t k = 0; k < n; ++k) {
+    if (cells[k] < 0 || cells[k] >= c->N) return set_err(c, LBM_E_ARG, "cell index out of range");
+    lev[k] = c->g.lev[cells[k]];
+    lbeg[lev[k] + 1]++;
+  }
+  for (int l = 0; l < c->L; ++l) lbeg[l + 1] += lbeg[l];
+  {
+    std::vector<int64_t> pos(lbeg.begin(), lbeg.end() - 1);
+    for (int64_t k = 0; k < n; ++k) {
+      const int64_t q = pos[lev[k]]++;
+      order[q] = k;
+      lst[q] = (int32_t)cells[k];
+    }
+  }
+  const size_t rows = (size_t)Q * (c->ddf ? 2 : 1);
+  const size_t need = rows * n + (c->lamf ? NLAM * n : 0) + (n + 1) / 2;
+  double *d = scratch(c, sizeof(double) * need);
+  if (!d) return set_err(c, LBM_E_NOMEM, "scratch allocation failed");
+  int32_t *dl = (int32_t *)(d + rows * n + (c->lamf ? NLAM * n : 0));
+  HIP_TRY(c, hipMemcpyAsync(dl, lst.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+  coalesce_all(c);
+  for (int l = 0; l < c->L; ++l) {
+    if (lbeg[l + 1] == lbeg[l]) continue;
+    MArgs a = gather_args(c, l, 3);
+    a.cells_list = dl;
+    a.slot_of = c->d_slot_of;
+    a.list_begin = lbeg[l];
+    a.count = lbeg[l + 1] - lbeg[l];
+    a.n = n;
+    a.out = d;
+    a.lam_out = c->lamf ? d + rows * n : nullptr;
+    c->ops.gather(a, c->pre[l], c->stream);
+  }
+  if ((s = check_launch(c)) != LBM_OK) return s;
+  std::vector<double> h(need - (n + 1) / 2);
+  HIP_TRY(c, hipMemcpyAsync(h.data(), d, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int64_t q = 0; q < n; ++q) {
+    const int64_t k = order[q];
+    for (int i = 0; i < Q; ++i) {
+      f[(size_t)i * n + k] = h[(size_t)i * n + q];
+      if (c->ddf) g[(size_t)i * n + k] = h[(size_t)(Q + i) * n + q];
+    }
+    if (c->lamf && lambda)
+      for (int a = 0; a < NLAM; ++a) lambda[(size_t)a * n + k] = h[rows * n + (size_t)a * n + q];
+  }
+  return LBM_OK;
+}
+
 lbm_status lbm_stats_get(lbm_ctx *c, lbm_stats *out) {
   lbm_status s = need_state(c);
   if (s != LBM_OK) return s;

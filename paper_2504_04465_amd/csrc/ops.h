@@ -118,7 +118,11 @@ struct MArgs {
   const int32_t *cell_of;  // [slot] canonical cell, -1 for holes
   int64_t begin, count;    // slots
   double cs2w, uw[6][3], Cv;
-  int mode;            // 0: moments, 1: populations (+ multipliers), 2: sums
+  int mode;            // 0: moments, 1: populations (+ multipliers), 2: sums,
+                       // 3: populations of listed cells
+  const int32_t *cells_list;  // mode 3: canonical cells, entries [list_begin, list_begin + count)
+  const int32_t *slot_of;     // mode 3: slot of a canonical cell
+  int64_t list_begin;
   double *out;         // moments [n_mom][n] / populations [Q][n] (g after)
   double *lam_out;     // [8][n]
   int64_t n;

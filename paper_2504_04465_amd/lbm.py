@@ -27,7 +27,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_MASK", -3: "LBM_E_NOMEM", -4:
 # every entry point declared in include/lbm.h
 EXPORTS = ["lbm_create", "lbm_grid_build", "lbm_grid_info", "lbm_layout_info", "lbm_grid_export", "lbm_init",
            "lbm_step", "lbm_set_face_bc", "lbm_moments", "lbm_moments_device", "lbm_stats_get",
-           "lbm_sync", "lbm_profile_enable", "lbm_profile_read", "lbm_get_state", "lbm_set_state",
+           "lbm_sync", "lbm_profile_enable", "lbm_profile_read", "lbm_get_state", "lbm_get_cells", "lbm_set_state",
            "lbm_last_error", "lbm_destroy", "lbm_mlp_set_weights", "lbm_mlp_get_weights",
            "lbm_mlp_label", "lbm_mlp_predict", "lbm_mlp_grad", "lbm_mlp_train"]
 MLP_PARAMS = 9176
@@ -97,6 +97,7 @@ def lib():
         L.lbm_profile_read.argtypes = [vp, C.c_int, vp, vp, vp]
         L.lbm_get_state.argtypes = [vp, vp, vp, vp]
         L.lbm_set_state.argtypes = [vp, vp, vp, vp]
+        L.lbm_get_cells.argtypes = [vp, vp, i64, vp, vp, vp]
         L.lbm_last_error.restype = C.c_char_p
         L.lbm_last_error.argtypes = [vp]
         L.lbm_destroy.argtypes = [vp]
@@ -269,15 +270,16 @@ class LBM:
         return dict(slots=ns.value, exception_rows=nx.value, slots_per_level=spl[: self.n_levels].tolist(),
                     rows_per_level=rpl[: self.n_levels].tolist())
 
-    def export(self):
+    def export(self, parts=("coords", "level", "flags", "nbr", "child", "bc_src")):
+        """canonical grid tables; `parts` selects which (the neighbour list of
+        a large grid is big)"""
         n, Q = self.n, self.Q
-        d = dict(coords=np.zeros((n, 3), np.int32), level=np.zeros(n, np.int8),
-                 flags=np.zeros(n, np.uint8), nbr=np.zeros((n, Q - 1), np.int32),
-                 child=np.zeros((self.n_ghosts, 1 << self.dim), np.int32),
-                 bc_src=np.zeros(n, np.int32))
-        self._check(self._L.lbm_grid_export(self.h, _ptr(d["coords"]), _ptr(d["level"]), _ptr(d["flags"]),
-                                            _ptr(d["nbr"]), _ptr(d["child"]), _ptr(d["bc_src"])),
-                    "lbm_grid_export")
+        shapes = dict(coords=((n, 3), np.int32), level=((n,), np.int8), flags=((n,), np.uint8),
+                      nbr=((n, Q - 1), np.int32), child=((self.n_ghosts, 1 << self.dim), np.int32),
+                      bc_src=((n,), np.int32))
+        d = {k: np.zeros(*shapes[k]) for k in parts}
+        ptrs = [_ptr(d[k]) if k in d else None for k in ("coords", "level", "flags", "nbr", "child", "bc_src")]
+        self._check(self._L.lbm_grid_export(self.h, *ptrs), "lbm_grid_export")
         return d
 
     def coords_levels(self):
@@ -340,6 +342,17 @@ class LBM:
         g = np.zeros((self.Q, self.n)) if self.ddf else None
         lam = np.zeros((8, self.n))
         self._check(self._L.lbm_get_state(self.h, _ptr(f), _ptr(g), _ptr(lam)), "lbm_get_state")
+        return f, g, lam
+
+    def get_cells(self, cells):
+        """state (f, g, lambda) of the listed canonical cells, [Q][n] each"""
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        n = cells.size
+        f = np.zeros((self.Q, n))
+        g = np.zeros((self.Q, n)) if self.ddf else None
+        lam = np.zeros((8, n))
+        self._check(self._L.lbm_get_cells(self.h, _ptr(cells), n, _ptr(f), _ptr(g) if g is not None else None,
+                                          _ptr(lam)), "lbm_get_cells")
         return f, g, lam
 
     def set_state(self, f, g=None, lam=None):
