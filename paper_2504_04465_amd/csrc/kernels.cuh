@@ -90,40 +90,6 @@ __device__ inline double wall_dot(const double (&uw)[6][3], int k, int i) {
 }
 
 // ---------------------------------------------------------------------------
-// pull of one population through an explicit row of pull sources; PRE: the
-// buffer still holds pre-collision values (after initialisation or a state
-// restore), so only coalesced slots move
-// ---------------------------------------------------------------------------
-template <class L, class S, bool PRE>
-__device__ inline typename Sto<S>::C pull_f(const S *fin, const int32_t *tab, int64_t tstride, int64_t row,
-                                            int64_t stride, int64_t vbase, int64_t c, int i,
-                                            const double (&uw)[6][3], double cs2w) {
-  using C = typename Sto<S>::C;
-  const int32_t s = tab[(int64_t)(i - 1) * tstride + row];
-  if (PRE) {
-    const int64_t src = ((int64_t)s >= vbase) ? (int64_t)s : c;
-    return Sto<S>::ld(fin, (int64_t)i * stride + src, L::S.w[i]);
-  }
-  if (s >= 0) return Sto<S>::ld(fin, (int64_t)i * stride + s, L::S.w[i]);
-  const int io = L::S.opp[i];
-  C v = Sto<S>::ld(fin, (int64_t)io * stride + c, L::S.w[io]);
-  if (s <= -2) v += (C)(2.0 * L::S.w[i] * wall_dot<L>(uw, -2 - s, i) / cs2w);
-  return v;
-}
-
-template <class L, class S, bool PRE>
-__device__ inline typename Sto<S>::C pull_g(const S *gin, const int32_t *tab, int64_t tstride, int64_t row,
-                                            int64_t stride, int64_t vbase, int64_t c, int i) {
-  const int32_t s = tab[(int64_t)(i - 1) * tstride + row];
-  if (PRE) {
-    const int64_t src = ((int64_t)s >= vbase) ? (int64_t)s : c;
-    return Sto<S>::ld(gin, (int64_t)i * stride + src, 0.0);
-  }
-  if (s >= 0) return Sto<S>::ld(gin, (int64_t)i * stride + s, 0.0);
-  return Sto<S>::ld(gin, (int64_t)L::S.opp[i] * stride + c, 0.0);
-}
-
-// ---------------------------------------------------------------------------
 // bricks: 64 cells (4x4x4 or 8x8) per wavefront, Z order inside the brick
 // ---------------------------------------------------------------------------
 template <class L>
@@ -150,6 +116,33 @@ __device__ inline int lane_bits(int p, int d) {
 #pragma unroll
   for (int b = 0; b < Brick<L>::SH; ++b) r |= ((p >> b) & 1) << (L::D * b + d);
   return r;
+}
+
+// Populations 1..Q-1 of cell c pulled through its explicit row: every
+// source is loaded before any is used, so the loads overlap.
+template <class L, class S, bool PRE, bool DDF>
+__device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnbr, int64_t xstride, int64_t row,
+                                  int64_t stride, int64_t vbase, int64_t c, const double (&uw)[6][3], double cs2w,
+                                  typename Sto<S>::C *f, typename Sto<S>::C *g) {
+  using C = typename Sto<S>::C;
+  int32_t sv[L::Q];
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) sv[i] = xnbr[(int64_t)(i - 1) * xstride + row];
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) {
+    const int32_t s = sv[i];
+    int64_t idx;
+    if (PRE) idx = (int64_t)i * stride + ((int64_t)s >= vbase ? (int64_t)s : c);
+    else idx = s >= 0 ? (int64_t)i * stride + s : (int64_t)L::S.opp[i] * stride + c;
+    // the lattice is symmetric: w of the opposite population is w_i
+    f[i] = Sto<S>::ld(fin, idx, L::S.w[i]);
+    if (DDF) g[i] = Sto<S>::ld(gin, idx, 0.0);
+  }
+  if (!PRE) {
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i)
+      if (sv[i] <= -2) f[i] += (C)(2.0 * L::S.w[i] * wall_dot<L>(uw, -2 - sv[i], i) / cs2w);
+  }
 }
 
 // Gather of the Q (2Q) populations a cell pulls (f_i from x - xi_i).
@@ -211,24 +204,7 @@ __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const 
     }
   } else {
     const int64_t row = tp.xbase[brick] + __popcll(xm & ((1ull << lane) - 1ull));
-    int32_t sv[L::Q];
-#pragma unroll
-    for (int i = 1; i < L::Q; ++i) sv[i] = tp.xnbr[(int64_t)(i - 1) * tp.xstride + row];
-#pragma unroll
-    for (int i = 1; i < L::Q; ++i) {
-      const int32_t s = sv[i];
-      int64_t idx;
-      if (PRE) idx = (int64_t)i * stride + ((int64_t)s >= vbase ? (int64_t)s : c);
-      else idx = s >= 0 ? (int64_t)i * stride + s : (int64_t)L::S.opp[i] * stride + c;
-      // the lattice is symmetric: w of the opposite population is w_i
-      f[i] = Sto<S>::ld(fin, idx, L::S.w[i]);
-      if (DDF) g[i] = Sto<S>::ld(gin, idx, 0.0);
-    }
-    if (!PRE) {
-#pragma unroll
-      for (int i = 1; i < L::Q; ++i)
-        if (sv[i] <= -2) f[i] += (C)(2.0 * L::S.w[i] * wall_dot<L>(uw, -2 - sv[i], i) / cs2w);
-    }
+    gather_row<L, S, PRE, DDF>(fin, gin, tp.xnbr, tp.xstride, row, stride, vbase, c, uw, cs2w, f, g);
   }
 }
 
@@ -849,14 +825,15 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
   S *fout = (S *)a.fout_coarse;
   S *gout = (S *)a.gout_coarse;
   const int64_t slot = a.vbase + gk;
+  // the child's populations as the fine level's next update pulls them
+  // (every child of a coarse ghost has an explicit row), all loads first
+  C f[L::Q], g[DDF ? L::Q : 1];
+  if (ch >= 0) gather_row<L, S, PRE, DDF>(fin, gin, a.xnbr, a.xstride, crow, a.stride, a.vbase, ch, a.uw, a.cs2w, f, g);
 #pragma unroll
   for (int i = 1; i < L::Q; ++i) {
     const bool need = (mask >> i) & 1ull;
-    C v = (C)0, vg = (C)0;
-    if (need && ch >= 0) {
-      v = pull_f<L, S, PRE>(fin, a.xnbr, a.xstride, crow, a.stride, a.vbase, ch, i, a.uw, a.cs2w);
-      if (DDF) vg = pull_g<L, S, PRE>(gin, a.xnbr, a.xstride, crow, a.stride, a.vbase, ch, i);
-    }
+    C v = (need && ch >= 0) ? f[i] : (C)0;
+    C vg = (DDF && need && ch >= 0) ? g[i] : (C)0;
     v = group_sum<NCH, C>(v);
     if (DDF) vg = group_sum<NCH, C>(vg);
     if (lead && need) {
@@ -889,14 +866,17 @@ __global__ void __launch_bounds__(BLOCK) k_explode(const EArgs a) {
   const int64_t G = a.ghost_cell[gk];
   const S *fin = (const S *)a.fin_coarse;
   S *fout = (S *)a.fout_fine;
+  S v[L::Q], vg[DDF ? L::Q : 1];
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) fout[(int64_t)i * a.stride + ch] = fin[(int64_t)i * a.stride + G];
-  if (DDF) {
-    const S *gin = (const S *)a.gin_coarse;
-    S *gout = (S *)a.gout_fine;
+  for (int i = 0; i < L::Q; ++i) v[i] = fin[(int64_t)i * a.stride + G];
+  if (DDF)
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) gout[(int64_t)i * a.stride + ch] = gin[(int64_t)i * a.stride + G];
-  }
+    for (int i = 0; i < L::Q; ++i) vg[i] = ((const S *)a.gin_coarse)[(int64_t)i * a.stride + G];
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) fout[(int64_t)i * a.stride + ch] = v[i];
+  if (DDF)
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) ((S *)a.gout_fine)[(int64_t)i * a.stride + ch] = vg[i];
   if (LAM)
 #pragma unroll
     for (int k = 0; k < NLAM; ++k) a.lam[(int64_t)k * a.stride + ch] = a.lam[(int64_t)k * a.stride + G];
@@ -936,12 +916,18 @@ __global__ void __launch_bounds__(BLOCK) k_bcfill(const BArgs a) {
 #pragma unroll
   for (int q = 0; q < 6; ++q)
     if (q == face) { fu[0] = a.fv.u[q][0]; fu[1] = a.fv.u[q][1]; fu[2] = a.fv.u[q][2]; }
-  if (kind < 0) {  // Neumann
+  if (kind < 0) {  // Neumann: all loads, then all stores
+    S v[L::Q], vg[DDF ? L::Q : 1];
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) f[(int64_t)i * a.stride + c] = f[(int64_t)i * a.stride + src];
+    for (int i = 0; i < L::Q; ++i) v[i] = f[(int64_t)i * a.stride + src];
     if (DDF)
 #pragma unroll
-      for (int i = 0; i < L::Q; ++i) g[(int64_t)i * a.stride + c] = g[(int64_t)i * a.stride + src];
+      for (int i = 0; i < L::Q; ++i) vg[i] = g[(int64_t)i * a.stride + src];
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) f[(int64_t)i * a.stride + c] = v[i];
+    if (DDF)
+#pragma unroll
+      for (int i = 0; i < L::Q; ++i) g[(int64_t)i * a.stride + c] = vg[i];
     if (LAM)
 #pragma unroll
       for (int q = 0; q < NLAM; ++q) a.lam[(int64_t)q * a.stride + c] = a.lam[(int64_t)q * a.stride + src];
