@@ -228,6 +228,41 @@ def surrogate_leg(args):
     return out
 
 
+def fp16_leg(w32, args):
+    """The same workload with FP16 populations (f - w_i stored, FP32
+    collisions): MLUPS and the collide kernel's algorithmic HBM rate."""
+    import torch
+    from paper_2504_04465_amd import lbm as B
+    from paper_2504_04465_amd import workloads as W
+    w = W.sphere(scale=args.scale, storage="fp16")
+    s = B.LBM.from_workload(w, storage="fp16")
+    s.init_workload(w)
+    s.step(args.warmup)
+    s.sync()
+    torch.cuda.synchronize()
+    s.profile(True)
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    s.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    L = s.n_levels
+    per_step = sum(int(n) << l for l, n in enumerate(s.n_per_level))
+    tb = tm = 0.0
+    ups = 0
+    for l in range(L):
+        n_l, ms_l, bpu = s.profile_read(l)
+        tb += bpu * int(s.n_per_level[l]) * n_l
+        tm += ms_l
+        ups += int(s.n_per_level[l]) * n_l
+    s.close()
+    ach = tb / (tm * 1e-3) / 1e9 if tm > 0 else 0.0
+    return {"value": round(per_step * args.steps / dt / 1e6, 2), "unit": "MLUPS",
+            "ms_per_step": round(dt / args.steps * 1e3, 4),
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_update": round(tb / max(ups, 1), 2)}}
+
+
 def calibrate_copy():
     """A plain copy of exactly 1 GiB (read 1 GiB, write 1 GiB) on the device:
     under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE it gives the factor between
@@ -256,6 +291,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--sur-scale", type=int, default=1)
     ap.add_argument("--sur-steps", type=int, default=8)
     ap.add_argument("--sur-develop", type=int, default=100)
@@ -363,6 +399,8 @@ def main():
                    "failures": st["newton_failures"]},
     }
     s.close()
+    if args.workload == "sphere" and storage == "fp32" and not args.no_fp16:
+        out["fp16_storage"] = fp16_leg(w, args)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(args)
     if not args.no_cpu_baseline:

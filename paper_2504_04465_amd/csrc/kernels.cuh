@@ -475,13 +475,69 @@ __device__ constexpr double mvec(int i, int a) {
 template <class L>
 __device__ inline void targets(double ux, double uy, double T, double *M);
 
+// Reflection orbits of a 2-D lattice symmetric under x -> -x and y -> -y:
+// representative k is the k-th velocity with c_x >= 0 and c_y >= 0.
+template <class L>
+__device__ constexpr int n_reps() {
+  int n = 0;
+  for (int i = 0; i < L::Q; ++i) n += (L::S.v[i].x >= 0 && L::S.v[i].y >= 0);
+  return n;
+}
+template <class L>
+__device__ constexpr int rep_of(int i) {
+  const int a = iabs_c(L::S.v[i].x), b = iabs_c(L::S.v[i].y);
+  int k = 0;
+  for (int j = 0; j < L::Q; ++j)
+    if (L::S.v[j].x >= 0 && L::S.v[j].y >= 0) {
+      if (L::S.v[j].x == a && L::S.v[j].y == b) return k;
+      ++k;
+    }
+  return -1;
+}
+template <class L>
+__device__ constexpr int rep_comp(int k, int d) {
+  int n = 0;
+  for (int j = 0; j < L::Q; ++j)
+    if (L::S.v[j].x >= 0 && L::S.v[j].y >= 0) {
+      if (n == k) return d == 0 ? L::S.v[j].x : L::S.v[j].y;
+      ++n;
+    }
+  return 0;
+}
+__device__ constexpr double ipow_c(int a, int p) {
+  double r = 1.0;
+  for (int k = 0; k < p; ++k) r *= a;
+  return r;
+}
+// m_a = sum of terms c x^p y^q: (1, x, y, x^2, xy, y^2, x^3 + x y^2, x^2 y + y^3)
+__device__ constexpr int mterms(int a) { return a >= 6 ? 2 : 1; }
+__device__ constexpr int mterm_p(int a, int t) {
+  return a == 0 ? 0 : a == 1 ? 1 : a == 2 ? 0 : a == 3 ? 2 : a == 4 ? 1 : a == 5 ? 0 : a == 6 ? (t ? 1 : 3)
+       : (t ? 0 : 2);
+}
+__device__ constexpr int mterm_q(int a, int t) {
+  return a == 0 ? 0 : a == 1 ? 0 : a == 2 ? 1 : a == 3 ? 0 : a == 4 ? 1 : a == 5 ? 2 : a == 6 ? (t ? 2 : 0)
+       : (t ? 3 : 1);
+}
+
+// One pass over the populations at multipliers lam (Eq. exponential):
+// e_i = exp(-(1 + lam . m_i)), the constraint residuals
+// G_a = sum_i e_i m_ia - M_a (Eqs. G0_8mom - G3yaa_8mom, per unit density)
+// and the Newton matrix H = sum_i e_i m_i m_i^T (packed lower triangle).
+// The sums go through the reflection orbits: per representative velocity
+// (a, b), the four sign-weighted sums P = sum e, sum s_x e, sum s_y e,
+// sum s_x s_y e over its members give every moment
+// S_pq = sum_i e_i c_x^p c_y^q = sum_k a^p b^q P_k[p mod 2, q mod 2],
+// and G, H are short sums of S.  e_i is kept only in the collision precision
+// C, for the final equilibrium.
 template <class L, class C, bool HESS = true>
 __device__ inline void expo_pass(const double *lam, double ux, double uy, double T, double *G, double *H, C *e) {
+  constexpr int NR = n_reps<L>();
+  double P[NR][4];
 #pragma unroll
-  for (int a = 0; a < NLAM; ++a) G[a] = 0.0;
-  if (HESS)
+  for (int k = 0; k < NR; ++k)
 #pragma unroll
-    for (int k = 0; k < NLAM * (NLAM + 1) / 2; ++k) H[k] = 0.0;
+    for (int t = 0; t < 4; ++t) P[k][t] = 0.0;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
     double s = 1.0;
@@ -490,20 +546,49 @@ __device__ inline void expo_pass(const double *lam, double ux, double uy, double
       if (mvec<L>(i, a) != 0.0) s += lam[a] * mvec<L>(i, a);
     const double ei = exp(-s);
     e[i] = (C)ei;
-#pragma unroll
-    for (int a = 0; a < NLAM; ++a) {
-      if (mvec<L>(i, a) == 0.0) continue;
-      G[a] += ei * mvec<L>(i, a);
-      if (!HESS) continue;
-#pragma unroll
-      for (int b = 0; b <= a; ++b)
-        if (mvec<L>(i, b) != 0.0) H[a * (a + 1) / 2 + b] += ei * (mvec<L>(i, a) * mvec<L>(i, b));
-    }
+    const int k = rep_of<L>(i);
+    const bool nx = L::S.v[i].x < 0, ny = L::S.v[i].y < 0;
+    P[k][0] += ei;
+    if (rep_comp<L>(k, 0) != 0) P[k][1] += nx ? -ei : ei;
+    if (rep_comp<L>(k, 1) != 0) P[k][2] += ny ? -ei : ei;
+    if (rep_comp<L>(k, 0) != 0 && rep_comp<L>(k, 1) != 0) P[k][3] += (nx != ny) ? -ei : ei;
   }
+  // S_pq for p + q <= 6
+  double S[7][7];
+#pragma unroll
+  for (int p = 0; p <= 6; ++p)
+#pragma unroll
+    for (int q = 0; p + q <= 6; ++q) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const double cf = ipow_c(rep_comp<L>(k, 0), p) * ipow_c(rep_comp<L>(k, 1), q);
+        if (cf != 0.0) acc += cf * P[k][(p & 1) | ((q & 1) << 1)];
+      }
+      S[p][q] = acc;
+    }
   double M[NLAM];
   targets<L>(ux, uy, T, M);
 #pragma unroll
-  for (int a = 0; a < NLAM; ++a) G[a] -= M[a];
+  for (int a = 0; a < NLAM; ++a) {
+    double g = 0.0;
+#pragma unroll
+    for (int t = 0; t < mterms(a); ++t) g += S[mterm_p(a, t)][mterm_q(a, t)];
+    G[a] = g - M[a];
+  }
+  if (HESS)
+#pragma unroll
+    for (int a = 0; a < NLAM; ++a)
+#pragma unroll
+      for (int b = 0; b <= a; ++b) {
+        double h = 0.0;
+#pragma unroll
+        for (int t = 0; t < mterms(a); ++t)
+#pragma unroll
+          for (int u = 0; u < mterms(b); ++u)
+            h += S[mterm_p(a, t) + mterm_p(b, u)][mterm_q(a, t) + mterm_q(b, u)];
+        H[a * (a + 1) / 2 + b] = h;
+      }
 }
 
 __device__ inline double nrm2_8(const double *G) {
@@ -537,7 +622,8 @@ __device__ inline void targets(double ux, double uy, double T, double *M) {
   M[7] = uy * (uu + 4.0 * T);
 }
 
-// d = H^-1 G by an in-place Cholesky factorisation of the packed H; false
+// d = H^-1 G by an in-place Cholesky factorisation of the packed H (the
+// diagonal holds the reciprocals 1 / L_jj, so the solves multiply); false
 // when H is not numerically positive definite
 __device__ inline bool cholesky_solve(double *H, const double *G, double *d) {
 #pragma unroll
@@ -546,9 +632,8 @@ __device__ inline bool cholesky_solve(double *H, const double *G, double *d) {
 #pragma unroll
     for (int k = 0; k < j; ++k) t -= H[j * (j + 1) / 2 + k] * H[j * (j + 1) / 2 + k];
     if (!(t > 0.0)) return false;
-    const double ljj = sqrt(t);
-    H[j * (j + 1) / 2 + j] = ljj;
-    const double inv = 1.0 / ljj;
+    const double inv = rsqrt(t);
+    H[j * (j + 1) / 2 + j] = inv;
 #pragma unroll
     for (int i = j + 1; i < NLAM; ++i) {
       double s = H[i * (i + 1) / 2 + j];
@@ -562,14 +647,14 @@ __device__ inline bool cholesky_solve(double *H, const double *G, double *d) {
     double s = G[i];
 #pragma unroll
     for (int k = 0; k < i; ++k) s -= H[i * (i + 1) / 2 + k] * d[k];
-    d[i] = s / H[i * (i + 1) / 2 + i];
+    d[i] = s * H[i * (i + 1) / 2 + i];
   }
 #pragma unroll
   for (int i = NLAM - 1; i >= 0; --i) {
     double s = d[i];
 #pragma unroll
     for (int k = i + 1; k < NLAM; ++k) s -= H[k * (k + 1) / 2 + i] * d[k];
-    d[i] = s / H[i * (i + 1) / 2 + i];
+    d[i] = s * H[i * (i + 1) / 2 + i];
   }
   return true;
 }
@@ -775,7 +860,28 @@ k_collide(const KArgs a) {
 #pragma unroll
         for (int k = 0; k < NLAM; ++k) lam[k] = (double)a.lam[(int64_t)k * stride + c];
       }
-      const int it = equilibrium_any<L, COLL, C>(rhop, u, T, a.ph, lam, a.ph.warm != 0, feq, geq);
+      int it;
+      if constexpr (COLL >= COLL_DDF_NEWTON) {
+        // park f and g in LDS while the Newton solve needs the registers
+        // (the memory clobbers keep the compiler from holding them anyway)
+        __shared__ C park[BLOCK / 64][2 * Q][64];
+        const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          park[wv][i][ln] = f[i];
+          park[wv][Q + i][ln] = g[i];
+        }
+        asm volatile("" ::: "memory");
+        it = equilibrium_any<L, COLL, C>(rhop, u, T, a.ph, lam, a.ph.warm != 0, feq, geq);
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          f[i] = park[wv][i][ln];
+          g[i] = park[wv][Q + i][ln];
+        }
+      } else {
+        it = equilibrium_any<L, COLL, C>(rhop, u, T, a.ph, lam, a.ph.warm != 0, feq, geq);
+      }
       if constexpr (COLL >= COLL_DDF_NEWTON) {
         count_add(a.counters, CNT_NEWTON_CALLS, 1);
         if (it < 0) count_add(a.counters, CNT_NEWTON_FAIL, 1);
