@@ -187,6 +187,17 @@ lbm_status lbm_step(lbm_ctx *ctx, int64_t n_coarse_steps);
  * effect for work enqueued afterwards. */
 lbm_status lbm_set_face_bc(lbm_ctx *ctx, int face, const lbm_face_bc *bc);
 
+/* Replay pairs of coarse steps from a HIP graph (on: 1) instead of launching
+ * every kernel (the scheduler of Sec. 4.5 issues ~10 launches per level per
+ * coarse step, which dominates on small grids).  Two coarse steps return
+ * every level's buffer parity to its start, so one captured graph serves
+ * every later pair while the parities, face values and grid are unchanged;
+ * it is re-captured otherwise.  lbm_step then advances pairs from the graph
+ * and single steps by launches; results are identical.  Off by default; not
+ * used while profiling.  The context's stream must not be the null stream
+ * (capture is refused there and lbm_step launches as usual). */
+lbm_status lbm_set_graphs(lbm_ctx *ctx, int on);
+
 /* Macroscopic fields of the state at the synchronisation point (pre-
  * collision populations, coarse ghosts with coalesced unknowns; fine ghosts
  * are NaN), written to the host array out [n_mom][n_cells].  Synchronous. */

@@ -71,6 +71,10 @@ struct lbm_ctx {
   void *d_mlp_ops = nullptr;
   float *d_mlp_loss = nullptr;
   bool have_mlp = false;
+  // graph replay of two coarse steps (launch-bound grids)
+  bool use_graphs = false;
+  hipGraphExec_t gexec = nullptr;
+  int gparity[8]{};
   // profiling
   bool prof = false;
   std::vector<ProfSlot> slots;
@@ -105,8 +109,16 @@ void *dev_alloc(lbm_ctx *c, size_t bytes) {
   return p;
 }
 
+void drop_graph(lbm_ctx *c) {
+  if (c->gexec) {
+    hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+}
+
 void free_device(lbm_ctx *c) {
   if (c->p.host_only) return;
+  drop_graph(c);
   if (!c->allocs.empty()) hipStreamSynchronize(c->stream);
   for (void *p : c->allocs) {
     if (c->dfree) c->dfree(p, c->actx);
@@ -723,30 +735,104 @@ lbm_status lbm_set_state(lbm_ctx *c, const double *f, const double *g, const dou
   return init_common(c, f, g, lambda, 1);
 }
 
+}  // extern "C"
+
+namespace {
+
+// one coarse step: 2^(L-1) finest substeps, active levels coarsest first
+void coarse_step(lbm_ctx *c) {
+  const int L = c->L;
+  for (int t = 0; t < (1 << (L - 1)); ++t) {
+    for (int l = 0; l < L; ++l) {
+      if (t % (1 << (L - 1 - l)) != 0) continue;
+      if (l + 1 < L) launch_coalesce(c, l);
+      launch_collide(c, l);
+      launch_bcfill(c, l);
+      if (l > 0 && t % (1 << (L - l)) == 0) launch_explode(c, l - 1);
+    }
+  }
+  c->coarse_steps++;
+}
+
+// Two coarse steps as one HIP graph: after two steps every level's buffer
+// parity is back where it was (level l flips 2^(l+1) times), so the
+// captured launches replay unchanged as long as the parities, the face
+// values and the context's buffers are those of the capture.
+bool graph_ready(lbm_ctx *c) {
+  for (int l = 0; l < c->L; ++l)
+    if (c->pre[l]) return false;
+  if (c->gexec) {
+    bool same = true;
+    for (int l = 0; l < c->L; ++l) same = same && c->gparity[l] == c->parity[l];
+    if (same) return true;
+    drop_graph(c);
+  }
+  int par[8];
+  int64_t upd[8], cs = c->coarse_steps;
+  for (int l = 0; l < 8; ++l) {
+    par[l] = c->parity[l];
+    upd[l] = c->updates[l];
+  }
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+  coarse_step(c);
+  coarse_step(c);
+  const hipError_t e = hipStreamEndCapture(c->stream, &g);
+  for (int l = 0; l < 8; ++l) {
+    c->parity[l] = par[l];
+    c->updates[l] = upd[l];
+  }
+  c->coarse_steps = cs;
+  if (e != hipSuccess || !g) {
+    hipGetLastError();
+    return false;
+  }
+  hipGraphExec_t x = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    hipGetLastError();
+    return false;
+  }
+  c->gexec = x;
+  for (int l = 0; l < c->L; ++l) c->gparity[l] = c->parity[l];
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
 lbm_status lbm_step(lbm_ctx *c, int64_t n) {
   lbm_status s = need_state(c);
   if (s != LBM_OK) return s;
   if (n < 0) return set_err(c, LBM_E_ARG, "negative step count");
   if (c->p.collision >= LBM_DDF_MLP && !c->have_mlp) return set_err(c, LBM_E_STATE, "surrogate weights not set");
-  const int L = c->L;
-  for (int64_t st = 0; st < n; ++st) {
-    for (int t = 0; t < (1 << (L - 1)); ++t) {
-      for (int l = 0; l < L; ++l) {
-        if (t % (1 << (L - 1 - l)) != 0) continue;
-        if (l + 1 < L) launch_coalesce(c, l);
-        launch_collide(c, l);
-        launch_bcfill(c, l);
-        if (l > 0 && t % (1 << (L - l)) == 0) launch_explode(c, l - 1);
-      }
+  while (n > 0) {
+    if (c->use_graphs && n >= 2 && !c->prof && graph_ready(c)) {
+      HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
+      for (int l = 0; l < c->L; ++l) c->updates[l] += 2 * (c->g.off[l + 1] - c->g.off[l]) << l;
+      c->coarse_steps += 2;
+      n -= 2;
+      continue;
     }
-    c->coarse_steps++;
+    coarse_step(c);
+    n -= 1;
   }
   return check_launch(c);
+}
+
+lbm_status lbm_set_graphs(lbm_ctx *c, int on) {
+  if (!c) return LBM_E_ARG;
+  c->use_graphs = on != 0;
+  if (!c->use_graphs) drop_graph(c);
+  return LBM_OK;
 }
 
 lbm_status lbm_set_face_bc(lbm_ctx *c, int face, const lbm_face_bc *bc) {
   if (!c || !bc || face < 0 || face > 5) return set_err(c, LBM_E_ARG, "bad face");
   if (c->have_grid && bc->kind != c->face[face].kind) return set_err(c, LBM_E_ARG, "face kind cannot change");
+  if (memcmp(&c->face[face], bc, sizeof *bc) != 0) drop_graph(c);  // the graph holds the face values
   c->face[face] = *bc;
   return LBM_OK;
 }
@@ -911,6 +997,7 @@ lbm_status lbm_sync(lbm_ctx *c) {
 
 lbm_status lbm_profile_enable(lbm_ctx *c, int on) {
   if (!c) return LBM_E_ARG;
+  drop_graph(c);
   c->prof = on != 0;
   if (c->prof)
     for (int l = 0; l < 8; ++l) {

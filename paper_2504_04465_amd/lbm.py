@@ -26,7 +26,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_MASK", -3: "LBM_E_NOMEM", -4:
 
 # every entry point declared in include/lbm.h
 EXPORTS = ["lbm_create", "lbm_grid_build", "lbm_grid_info", "lbm_layout_info", "lbm_grid_export", "lbm_init",
-           "lbm_step", "lbm_set_face_bc", "lbm_moments", "lbm_moments_device", "lbm_stats_get",
+           "lbm_step", "lbm_set_face_bc", "lbm_set_graphs", "lbm_moments", "lbm_moments_device", "lbm_stats_get",
            "lbm_sync", "lbm_profile_enable", "lbm_profile_read", "lbm_get_state", "lbm_get_cells", "lbm_set_state",
            "lbm_last_error", "lbm_destroy", "lbm_mlp_set_weights", "lbm_mlp_get_weights",
            "lbm_mlp_label", "lbm_mlp_predict", "lbm_mlp_grad", "lbm_mlp_train"]
@@ -89,6 +89,7 @@ def lib():
         L.lbm_init.argtypes = [vp, vp]
         L.lbm_step.argtypes = [vp, i64]
         L.lbm_set_face_bc.argtypes = [vp, C.c_int, C.POINTER(FaceBC)]
+        L.lbm_set_graphs.argtypes = [vp, C.c_int]
         L.lbm_moments.argtypes = [vp, vp]
         L.lbm_moments_device.argtypes = [vp, vp]
         L.lbm_stats_get.argtypes = [vp, C.POINTER(Stats)]
@@ -187,7 +188,9 @@ class LBM:
             if not torch.cuda.is_available():
                 raise RuntimeError("no GPU visible: liblbm.so needs a device (or host_only=True)")
             torch.cuda.set_device(device)
-            self.torch_stream = stream if stream is not None else torch.cuda.current_stream(device)
+            # a stream of the context's own (default priority): graph capture
+            # needs a stream other than the null stream
+            self.torch_stream = stream if stream is not None else torch.cuda.Stream(device)
             stream_ptr = self.torch_stream.cuda_stream
             self._alloc = _TorchAlloc(device, stream_ptr)
             alloc_cb, free_cb = self._alloc.alloc_cb, self._alloc.free_cb
@@ -305,16 +308,25 @@ class LBM:
         f = face_struct(face)
         self._check(self._L.lbm_set_face_bc(self.h, k, C.byref(f)), "lbm_set_face_bc")
 
+    def graphs(self, on=True):
+        """replay pairs of coarse steps from a HIP graph"""
+        self._check(self._L.lbm_set_graphs(self.h, int(on)), "lbm_set_graphs")
+
     def moments(self):
         out = np.zeros((self.n_mom, self.n))
         self._check(self._L.lbm_moments(self.h, _ptr(out)), "lbm_moments")
         return out
 
     def moments_device(self, out_tensor):
-        """enqueue the moments into a CUDA tensor of n_mom * n float64."""
+        """enqueue the moments into a CUDA tensor of n_mom * n float64; the
+        caller's current stream waits for them"""
+        import torch
         assert out_tensor.numel() >= self.n_mom * self.n
+        out_tensor.record_stream(self.torch_stream)
+        self.torch_stream.wait_stream(torch.cuda.current_stream(out_tensor.device))
         self._check(self._L.lbm_moments_device(self.h, C.c_void_p(out_tensor.data_ptr())),
                     "lbm_moments_device")
+        torch.cuda.current_stream(out_tensor.device).wait_stream(self.torch_stream)
 
     def stats(self):
         s = Stats()
