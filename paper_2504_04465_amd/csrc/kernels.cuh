@@ -120,16 +120,18 @@ __device__ inline int lane_bits(int p, int d) {
 
 // Populations 1..Q-1 of cell c pulled through its explicit row: every
 // source is loaded before any is used, so the loads overlap.
+// Populations not in `want` (bit i) are neither loaded nor set.
 template <class L, class S, bool PRE, bool DDF>
 __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnbr, int64_t xstride, int64_t row,
                                   int64_t stride, int64_t vbase, int64_t c, const double (&uw)[6][3], double cs2w,
-                                  typename Sto<S>::C *f, typename Sto<S>::C *g) {
+                                  typename Sto<S>::C *f, typename Sto<S>::C *g, uint64_t want = ~0ull) {
   using C = typename Sto<S>::C;
   int32_t sv[L::Q];
 #pragma unroll
-  for (int i = 1; i < L::Q; ++i) sv[i] = xnbr[(int64_t)(i - 1) * xstride + row];
+  for (int i = 1; i < L::Q; ++i) sv[i] = ((want >> i) & 1ull) ? xnbr[(int64_t)(i - 1) * xstride + row] : 0;
 #pragma unroll
   for (int i = 1; i < L::Q; ++i) {
+    if (!((want >> i) & 1ull)) continue;
     const int32_t s = sv[i];
     int64_t idx;
     if (PRE) idx = (int64_t)i * stride + ((int64_t)s >= vbase ? (int64_t)s : c);
@@ -141,7 +143,7 @@ __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnb
   if (!PRE) {
 #pragma unroll
     for (int i = 1; i < L::Q; ++i)
-      if (sv[i] <= -2) f[i] += (C)(2.0 * L::S.w[i] * wall_dot<L>(uw, -2 - sv[i], i) / cs2w);
+      if (((want >> i) & 1ull) && sv[i] <= -2) f[i] += (C)(2.0 * L::S.w[i] * wall_dot<L>(uw, -2 - sv[i], i) / cs2w);
   }
 }
 
@@ -934,7 +936,8 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
   // the child's populations as the fine level's next update pulls them
   // (every child of a coarse ghost has an explicit row), all loads first
   C f[L::Q], g[DDF ? L::Q : 1];
-  if (ch >= 0) gather_row<L, S, PRE, DDF>(fin, gin, a.xnbr, a.xstride, crow, a.stride, a.vbase, ch, a.uw, a.cs2w, f, g);
+  if (ch >= 0)
+    gather_row<L, S, PRE, DDF>(fin, gin, a.xnbr, a.xstride, crow, a.stride, a.vbase, ch, a.uw, a.cs2w, f, g, mask);
 #pragma unroll
   for (int i = 1; i < L::Q; ++i) {
     const bool need = (mask >> i) & 1ull;
