@@ -101,8 +101,8 @@ __global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
     S *gout = (S *)a.gout;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      Sto<S>::st(fout, (int64_t)i * stride + c, f[i], L::S.w[i]);
-      Sto<S>::st(gout, (int64_t)i * stride + c, g[i], 0.0);
+      Sto<S>::stn(fout, (int64_t)i * stride + c, f[i], L::S.w[i]);
+      Sto<S>::stn(gout, (int64_t)i * stride + c, g[i], 0.0);
     }
   }
 }

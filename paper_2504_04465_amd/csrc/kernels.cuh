@@ -28,7 +28,10 @@ namespace lbm {
 constexpr int BLOCK = 256;
 
 // ---------------------------------------------------------------------------
-// storage traits: FP64, FP32, FP16 holding f_i - w_i (compute in FP32)
+// storage traits: FP64, FP32, FP16 holding f_i - w_i (compute in FP32).
+// stn is a streaming (non-temporal) store: the collide kernel's output is not
+// read again before the level's next update, so it should not displace the
+// neighbour lines that other wavefronts still pull from the L2.
 // ---------------------------------------------------------------------------
 template <class S>
 struct Sto;
@@ -38,6 +41,7 @@ struct Sto<double> {
   __device__ static C ld(const double *p, int64_t k, double) { return p[k]; }
   __device__ static C ldv(double v, double) { return v; }
   __device__ static void st(double *p, int64_t k, C v, double) { p[k] = v; }
+  __device__ static void stn(double *p, int64_t k, C v, double) { __builtin_nontemporal_store(v, p + k); }
 };
 template <>
 struct Sto<float> {
@@ -45,6 +49,7 @@ struct Sto<float> {
   __device__ static C ld(const float *p, int64_t k, double) { return p[k]; }
   __device__ static C ldv(float v, double) { return v; }
   __device__ static void st(float *p, int64_t k, C v, double) { p[k] = v; }
+  __device__ static void stn(float *p, int64_t k, C v, double) { __builtin_nontemporal_store(v, p + k); }
 };
 template <>
 struct Sto<__half> {
@@ -55,6 +60,9 @@ struct Sto<__half> {
   __device__ static C ldv(__half v, double w) { return __half2float(v) + (float)w; }
   __device__ static void st(__half *p, int64_t k, C v, double w) {
     p[k] = __float2half_rn(v - (float)w);
+  }
+  __device__ static void stn(__half *p, int64_t k, C v, double w) {
+    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v - (float)w)), (unsigned short *)p + k);
   }
 };
 
@@ -905,8 +913,8 @@ k_collide(const KArgs a) {
   S *gout = (S *)a.gout;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    Sto<S>::st(fout, (int64_t)i * stride + c, f[i], L::S.w[i]);
-    if (DDF) Sto<S>::st(gout, (int64_t)i * stride + c, g[i], 0.0);
+    Sto<S>::stn(fout, (int64_t)i * stride + c, f[i], L::S.w[i]);
+    if (DDF) Sto<S>::stn(gout, (int64_t)i * stride + c, g[i], 0.0);
   }
 }
 
@@ -920,12 +928,22 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
   using C = typename Sto<S>::C;
   constexpr int NCH = 1 << L::D;
   const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  const int64_t gl = t / NCH;
+  // lanes (ghost, group, child): group k of ngrp takes the populations
+  // i = k mod ngrp, so that a small interface still spreads over many
+  // compute units
+  const int64_t q = t / NCH;
+  const int64_t gl = q / a.ngrp;
+  const int grp = (int)(q % a.ngrp);
   const bool valid = gl < a.count;
   const int64_t gk = a.g0 + gl;
   const int32_t ch = valid ? a.child[gk * NCH + (t % NCH)] : -1;
   const int32_t crow = ch >= 0 ? a.crow[gk * NCH + (t % NCH)] : 0;
-  const uint64_t mask = valid ? a.unknown[gk] : 0ull;
+  uint64_t mask = valid ? a.unknown[gk] : 0ull;
+  if (a.ngrp > 1) {
+    uint64_t sel = 0ull;
+    for (int i = grp; i < L::Q; i += a.ngrp) sel |= 1ull << i;
+    mask &= sel;
+  }
   const bool lead = valid && (t % NCH) == 0;
   const C nf = group_sum<NCH, C>(ch >= 0 ? (C)1 : (C)0);
   const S *fin = (const S *)a.fin_child;
@@ -951,12 +969,14 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
     }
   }
   if (LAM) {
-    const int64_t G = valid ? a.ghost_cell[gk] : 0;
+    // the multipliers go with group 0 (a group's NCH lanes agree on it)
+    const bool mine = grp == 0;
+    const int64_t G = valid && mine ? a.ghost_cell[gk] : 0;
 #pragma unroll
     for (int k = 0; k < NLAM; ++k) {
-      double v = ch >= 0 ? (double)a.lam[(int64_t)k * a.stride + ch] : 0.0;
+      double v = ch >= 0 && mine ? (double)a.lam[(int64_t)k * a.stride + ch] : 0.0;
       v = group_sum<NCH, double>(v);
-      if (lead) a.lam[(int64_t)k * a.stride + G] = (float)(v / (double)nf);
+      if (lead && mine) a.lam[(int64_t)k * a.stride + G] = (float)(v / (double)nf);
     }
   }
 }
@@ -1224,9 +1244,14 @@ struct Launch {
     if (pre) hipLaunchKernelGGL((k_collide<L, COLL, S, true>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
     else hipLaunchKernelGGL((k_collide<L, COLL, S, false>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
   }
-  static void coalesce(const CArgs &a, bool pre, hipStream_t s) {
-    if (a.count <= 0) return;
-    const int64_t work = a.count << L::D;
+  static void coalesce(const CArgs &a0, bool pre, hipStream_t s) {
+    if (a0.count <= 0) return;
+    // split the populations of a child over up to 8 lanes while the
+    // interface is too small to give every compute unit a workgroup
+    CArgs a = a0;
+    const int64_t lanes = a.count << L::D;
+    a.ngrp = (int)std::min<int64_t>(8, std::max<int64_t>(1, (256 * BLOCK) / lanes));
+    const int64_t work = lanes * a.ngrp;
     if (pre) hipLaunchKernelGGL((k_coalesce<L, S, true, DDF, LAM>), dim3(nblocks(work)), dim3(BLOCK), 0, s, a);
     else hipLaunchKernelGGL((k_coalesce<L, S, false, DDF, LAM>), dim3(nblocks(work)), dim3(BLOCK), 0, s, a);
   }

@@ -79,6 +79,7 @@ struct CArgs {
   const int32_t *ghost_cell;
   int64_t g0, count;        // ghosts [g0, g0 + count)
   double cs2w, uw[6][3];
+  int ngrp;                 // population groups per child (set by the launcher)
 };
 
 // uniform explosion of coarse-ghost post-collision states into the children
