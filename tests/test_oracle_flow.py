@@ -1,7 +1,8 @@
 """Flow-level pins of the oracle: identity with an independent Cartesian
 update on a uniform grid, conservation across refinement interfaces, uniform
 states preserved, analytic shear-wave decay (uniform and refined), Couette
-flow, and the Sod shock tube against the exact Riemann solution."""
+and Poiseuille flow (uniform and refined along the walls), and the Sod shock
+tube against the exact Riemann solution."""
 import math
 
 import numpy as np
@@ -166,6 +167,70 @@ def test_couette_linear_profile():
     y = e["coords"][:, 1]
     assert np.max(np.abs(m[1] - U * (y + 0.5) / H)) < 1e-6 * U
     assert np.max(np.abs(m[2])) < 1e-9
+
+
+def channel_flow(H, coll, levels):
+    """Channel of height H and length 6H between bounce-back walls: the
+    equilibrium inflow face imposes (rho = 1, u = U), the outflow face
+    imposes u = U with the density taken from the fluid (a zero-gradient
+    outflow would forbid the pressure drop the flow needs).  With two
+    levels, strips of H/4 along both walls are refined over the middle half
+    of the channel.  Returns the velocity profile u(y) (cell centres in
+    coarse units) of the middle coarse column, the mean velocity there, and
+    (one level) the density slope and mean mass flux along the middle half."""
+    nx, U, nu = 6 * H, 0.02, 0.1
+    w = W.shear(n=nx, levels=levels, lattice="D2Q9", collision=coll, nu_finest=nu)
+    w.ext = (nx, H)
+    if levels == 2:
+        lo = W._box_mask(w.ext, 2, 0, (nx // 4, 0), (3 * nx // 4, H // 4))
+        hi = W._box_mask(w.ext, 2, 0, (nx // 4, 3 * H // 4), (3 * nx // 4, H))
+        w.refine = [np.logical_or(lo, hi)]
+    w.faces = [W.Face("equilibrium", rho=1.0, u=(U, 0, 0)),
+               W.Face("equilibrium", u=(U, 0, 0), extrapolate_rho=True),
+               W.Face("wall"), W.Face("wall"), W.Face(), W.Face()]
+    w.init = lambda c, l: np.vstack([np.ones(len(c)), np.full(len(c), U), np.zeros(len(c))])
+    o = Oracle.from_workload(w)
+    o.init_workload(w)
+    o.step(40 * H * H)  # ~13 viscous times H^2 / nu of the coarse level
+    e, m = o.export(), o.moments()
+    x, y, lev = e["coords"][:, 0], e["coords"][:, 1], e["level"].astype(np.int64)
+    ok = ~np.isnan(m[0])
+    ys, us, hs = [], [], []
+    for l in range(levels):
+        sel = ok & (lev == l) & ((x >> l) == nx // 2)
+        for yy in np.unique(y[sel]):
+            t = sel & (y == yy)
+            ys.append((yy + 0.5) / 2 ** l)
+            us.append(m[1][t].mean())
+            hs.append(1.0 / 2 ** l)
+    ys, us, hs = map(np.array, (ys, us, hs))
+    ubar = float(np.sum(us * hs) / H)
+    cols = np.arange(nx // 4, 3 * nx // 4)
+    slope = flux = None
+    if levels == 1:
+        rho = [m[0][x == k].mean() for k in cols]
+        slope = float(np.polyfit(cols, rho, 1)[0])
+        flux = float(np.mean([(m[0] * m[1])[x == k].mean() for k in cols]))
+    return ys, us, ubar, slope, flux, nu
+
+
+@pytest.mark.parametrize("coll,levels", [("RR", 1), ("BGK", 1), ("RR", 2)])
+def test_poiseuille_profile_second_order(coll, levels):
+    """Developed channel flow: u(y) / ubar = 6 eta (1 - eta), eta = y / H
+    with the walls half-way between the wall cells and the solid, reached at
+    second order in the resolution (also with the walls on a finer level);
+    and the pressure drop of the plane Poiseuille law, -dp/dx = 12 mu ubar
+    / H^2 with p = rho c_s^2 and mu = rho nu (rho ubar: the mass flux)."""
+    dev = {}
+    for H in (8, 16):
+        ys, us, ubar, slope, flux, nu = channel_flow(H, coll, levels)
+        eta = ys / H
+        dev[H] = float(np.max(np.abs(us / ubar - 6 * eta * (1 - eta))))
+        if slope is not None:
+            pred = -12.0 * nu * flux / H ** 2 / (1.0 / 3.0)
+            assert abs(slope / pred - 1) < 0.02, (H, slope, pred)
+    assert dev[16] < 5e-3, dev
+    assert dev[8] / dev[16] > 3.2, dev
 
 
 def sod_error(nx):
