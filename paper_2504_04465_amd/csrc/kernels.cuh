@@ -791,7 +791,7 @@ __device__ inline int equilibrium_any(C rho, const C *u, C T, const PhysArgs &ph
 }
 
 __device__ inline void count_add(unsigned long long *ctr, int which, unsigned long long v) {
-  if (v) atomicAdd(ctr + which, v);
+  if (v) atomicAdd(ctr + CNT_COUNT * (blockIdx.x & (CNT_COPIES - 1u)) + which, v);
 }
 
 // ---------------------------------------------------------------------------

@@ -322,10 +322,14 @@ lbm_status check_launch(lbm_ctx *c) {
   return LBM_OK;
 }
 
+// the counters, summed over their copies
 lbm_status read_counters(lbm_ctx *c, unsigned long long *out) {
-  HIP_TRY(c, hipMemcpyAsync(out, c->d_counters, CNT_COUNT * sizeof(unsigned long long),
+  std::vector<unsigned long long> h((size_t)CNT_COUNT * CNT_COPIES);
+  HIP_TRY(c, hipMemcpyAsync(h.data(), c->d_counters, h.size() * sizeof(unsigned long long),
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < CNT_COUNT; ++k) out[k] = 0;
+  for (size_t j = 0; j < h.size(); ++j) out[j % CNT_COUNT] += h[j];
   return LBM_OK;
 }
 
@@ -617,9 +621,9 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
   if ((s = upload(c, &c->d_unknown, c->g.unknown.data(), c->Ng)) != LBM_OK) return s;
   if ((s = upload(c, &c->d_bc_face, c->g.bc_face.data(), c->g.bc_face.size())) != LBM_OK) return s;
   (void)NCH;
-  c->d_counters = (unsigned long long *)dev_alloc(c, sizeof(unsigned long long) * CNT_COUNT);
+  c->d_counters = (unsigned long long *)dev_alloc(c, sizeof(unsigned long long) * CNT_COUNT * CNT_COPIES);
   if (!c->d_counters) return set_err(c, LBM_E_NOMEM, "counter allocation failed");
-  HIP_TRY(c, hipMemset(c->d_counters, 0, sizeof(unsigned long long) * CNT_COUNT));
+  HIP_TRY(c, hipMemset(c->d_counters, 0, sizeof(unsigned long long) * CNT_COUNT * CNT_COPIES));
   return LBM_OK;
 }
 
@@ -695,7 +699,7 @@ static lbm_status init_common(lbm_ctx *c, const double *src, const double *src_g
     dl = d + rows * n * (c->ddf ? 2 : 1);
     HIP_TRY(c, hipMemcpyAsync(dl, src_lam, sizeof(double) * NLAM * n, hipMemcpyHostToDevice, c->stream));
   }
-  HIP_TRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long) * CNT_COUNT, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long) * CNT_COUNT * CNT_COPIES, c->stream));
   IArgs a{};
   a.f = c->f[0];
   a.g = c->gb[0];

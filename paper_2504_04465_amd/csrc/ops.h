@@ -12,9 +12,13 @@ enum CollisionKind { COLL_BGK = 0, COLL_RR = 1, COLL_DDF_POLY = 2, COLL_DDF_NEWT
                      COLL_DDF_MLP = 4, COLL_DDF_MLP_NEWTON = 5 };
 enum StorageKind { STO_FP64 = 0, STO_FP32 = 1, STO_FP16 = 2 };
 
-// device counters (unsigned long long)
+// device counters (unsigned long long), CNT_COPIES copies of CNT_COUNT (one
+// 64-byte line each): a block adds to copy blockIdx mod CNT_COPIES, the host
+// sums the copies.  Every Newton cell counts its solve; with one copy, the
+// atomics of all wavefronts of the device queued on a single line and took
+// two thirds of the D2Q21 collide's time.
 enum { CNT_NEWTON_CALLS = 0, CNT_NEWTON_ITERS = 1, CNT_NEWTON_FAIL = 2, CNT_NONFINITE = 3,
-       CNT_MLP_FALLBACK = 4, CNT_COUNT = 8 };
+       CNT_MLP_FALLBACK = 4, CNT_COUNT = 8, CNT_COPIES = 1024 };
 
 constexpr int NLAM = 8;
 constexpr int MLP_IN = 4, MLP_HID = 64, MLP_OUT = 8;
