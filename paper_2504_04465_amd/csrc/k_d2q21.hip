@@ -12,6 +12,10 @@ using L21 = Lattice<LAT_D2Q21>;
 // for its 64 cells (two 32-cell tiles on the matrix cores), then each cell
 // takes the predicted multipliers (DDF_MLP), or one Newton correction from
 // them with a full Newton fallback above fallback_tol (DDF_MLP_NEWTON).
+// The populations are pulled twice: for the moments, and again (from the
+// caches) for the collision, so that they are not live across the MLP and
+// the Newton solve; holding them needs 284 registers, one wavefront per SIMD
+// instead of two.
 template <int COLL, class S, bool PRE>
 __global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
   using L = L21;
@@ -30,13 +34,19 @@ __global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
   const uint8_t fl = live ? a.flags[c] : (uint8_t)F_HOLE;
   const bool valid = !(fl & F_HOLE);
   const int64_t stride = a.stride;
-  C f[Q], g[Q];
   C rho = (C)1, u[3] = {(C)0, (C)0, (C)0}, T = (C)1;
   if (valid) {
+    C f[Q], g[Q];
     gather<L, S, PRE, true>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[w], stride, a.vbase, c, l, brick,
                             a.topo.xmask[brick], a.ph.uw, a.ph.cs2w, f, g);
     cell_moments<L, C, true>(f, g, (C)a.ph.Cv, rho, u, T);
   }
+  // the populations again, after the equilibrium (no code motion across)
+  auto pull = [&](C *f, C *g) {
+    asm volatile("" ::: "memory");
+    gather<L, S, PRE, true>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[w], stride, a.vbase, c, l, brick,
+                            a.topo.xmask[brick], a.ph.uw, a.ph.cs2w, f, g);
+  };
   const bool collide = valid && !(fl & (F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ));
   // the multipliers depend on (u, T) only; non-colliding lanes feed a benign state
   float cux = collide ? (float)u[0] : 0.0f, cuy = collide ? (float)u[1] : 0.0f;
@@ -64,14 +74,17 @@ __global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
       // corrected multipliers to newton_tol (from zero if the correction
       // itself failed)
       count_add(a.counters, CNT_NEWTON_CALLS, 1);
-      int it = newton_lean<L, C>((double)u[0], (double)u[1], (double)T, lam, a.ph.newton_tol, a.ph.newton_max_it, 1,
-                                 a.ph.fallback_tol, e);
-      if (it != 1) count_add(a.counters, CNT_MLP_FALLBACK, 1);
-      if (it < 0) {
+      // one call site for both attempts (a second inlined solver would
+      // raise the kernel's register need)
+      int it = -1;
+      for (int attempt = 0; attempt < 2; ++attempt) {
+        if (attempt == 1)
 #pragma unroll
-        for (int k = 0; k < NLAM; ++k) lam[k] = 0.0;
-        it = newton_lean<L, C>((double)u[0], (double)u[1], (double)T, lam, a.ph.newton_tol, a.ph.newton_max_it, 0,
-                               a.ph.newton_tol, e);
+          for (int k = 0; k < NLAM; ++k) lam[k] = 0.0;
+        it = newton_lean<L, C>((double)u[0], (double)u[1], (double)T, lam, a.ph.newton_tol, a.ph.newton_max_it,
+                               attempt == 0 ? 1 : 0, attempt == 0 ? a.ph.fallback_tol : a.ph.newton_tol, e);
+        if (attempt == 0 && it != 1) count_add(a.counters, CNT_MLP_FALLBACK, 1);
+        if (it >= 0) break;
       }
       if (it < 0) count_add(a.counters, CNT_NEWTON_FAIL, 1);
       else count_add(a.counters, CNT_NEWTON_ITERS, (unsigned long long)it);
@@ -87,16 +100,22 @@ __global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
       feq[i] = rhop * e[i];
       geq[i] = kg * feq[i];
     }
+    C f[Q], g[Q];
+    pull(f, g);
     C te = (C)a.ph.tau;
     if (a.ph.sensor_on) te *= sensor_alpha<L, C>(f, feq, te, (C)a.ph.sensor_A);
     const C om = (C)1 / te;
+    S *fout = (S *)a.fout;
+    S *gout = (S *)a.gout;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      f[i] = f[i] - om * (f[i] - feq[i]);
-      g[i] = g[i] - om * (g[i] - geq[i]);
+      Sto<S>::stn(fout, (int64_t)i * stride + c, f[i] - om * (f[i] - feq[i]), L::S.w[i]);
+      Sto<S>::stn(gout, (int64_t)i * stride + c, g[i] - om * (g[i] - geq[i]), 0.0);
     }
-  }
-  if (valid) {
+  } else if (valid) {
+    // fine ghosts and boundary layers: streamed, not collided
+    C f[Q], g[Q];
+    pull(f, g);
     S *fout = (S *)a.fout;
     S *gout = (S *)a.gout;
 #pragma unroll
