@@ -12,6 +12,7 @@ import pytest
 from oracle.oracle import Oracle
 from paper_2504_04465_amd import lbm as B
 from paper_2504_04465_amd import workloads as W
+from edge_cases import edge_cases
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -45,7 +46,7 @@ def cases():
     w.refine[0].data[:] = m[4:20, 0:22]
     w.faces = [W.Face("wall"), W.Face("wall"), W.Face("periodic"), W.Face("periodic"), W.Face(), W.Face()]
     out.append(("blob", w))
-    return out
+    return out + edge_cases()
 
 
 @pytest.mark.parametrize("name,w", cases(), ids=[c[0] for c in cases()])
