@@ -807,14 +807,25 @@ struct MinWaves {
   static constexpr int value = COLL < COLL_DDF_POLY ? (sizeof(S) == 8 ? 4 : 6) : (COLL >= COLL_DDF_NEWTON ? 2 : 1);
 };
 
+// Block size of the collide kernel: in 3-D one block is the 2 x 2 x 2 cube
+// of bricks that is consecutive in Z order; the barrier after the table
+// staging releases its eight wavefronts together, so their pulls from each
+// other's bricks meet in the L2 (1 % faster than four bricks per block on
+// the sphere; in 2-D four bricks are better).
+template <class L, int COLL>
+struct CollideBlock {
+  static constexpr int value = (L::D == 3 && COLL < COLL_DDF_POLY) ? 512 : BLOCK;
+};
+
 template <class L, int COLL, class S, bool PRE>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MinWaves<L, COLL, S>::value)))
-k_collide(const KArgs a) {
+__global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
+    __attribute__((amdgpu_waves_per_eu(MinWaves<L, COLL, S>::value))) k_collide(const KArgs a) {
   using C = typename Sto<S>::C;
   constexpr bool DDF = COLL >= COLL_DDF_POLY;
   constexpr int Q = L::Q;
-  __shared__ uint32_t nbs[BLOCK / 64][Brick<L>::NBP];
-  const int64_t t = xcd_block() * BLOCK + threadIdx.x;
+  constexpr int CB = CollideBlock<L, COLL>::value;
+  __shared__ uint32_t nbs[CB / 64][Brick<L>::NBP];
+  const int64_t t = xcd_block() * CB + threadIdx.x;
   const bool live = t < a.count;  // whole wavefronts
   const int64_t c = a.begin + (live ? t : 0);
   const int32_t brick = stage_bricks<L, S>(a.topo, nbs, c, live);
@@ -1241,8 +1252,10 @@ struct Launch {
   static constexpr bool LAM = COLL >= COLL_DDF_NEWTON;
   static void collide(const KArgs &a, bool pre, hipStream_t s) {
     if (a.count <= 0) return;
-    if (pre) hipLaunchKernelGGL((k_collide<L, COLL, S, true>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
-    else hipLaunchKernelGGL((k_collide<L, COLL, S, false>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
+    constexpr int CB = CollideBlock<L, COLL>::value;
+    const unsigned nb = (unsigned)((a.count + CB - 1) / CB);
+    if (pre) hipLaunchKernelGGL((k_collide<L, COLL, S, true>), dim3(nb), dim3(CB), 0, s, a);
+    else hipLaunchKernelGGL((k_collide<L, COLL, S, false>), dim3(nb), dim3(CB), 0, s, a);
   }
   static void coalesce(const CArgs &a0, bool pre, hipStream_t s) {
     if (a0.count <= 0) return;
