@@ -962,21 +962,47 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
   S *fout = (S *)a.fout_coarse;
   S *gout = (S *)a.gout_coarse;
   const int64_t slot = a.vbase + gk;
-  // the child's populations as the fine level's next update pulls them
-  // (every child of a coarse ghost has an explicit row), all loads first
-  C f[L::Q], g[DDF ? L::Q : 1];
-  if (ch >= 0)
-    gather_row<L, S, PRE, DDF>(fin, gin, a.xnbr, a.xstride, crow, a.stride, a.vbase, ch, a.uw, a.cs2w, f, g, mask);
+  if (a.ngrp > 1) {
+    // a small interface: the lane's own populations one at a time.  The
+    // unrolled path below is tens of KB of code for the wide lattices, and
+    // its cold instruction fetch dominates a launch of a few workgroups.
+    // The NCH lanes of a group share grp and so the trip count.
+    for (int i = grp == 0 ? a.ngrp : grp; i < L::Q; i += a.ngrp) {
+      const bool need = (mask >> i) & 1ull;
+      C v = (C)0, vg = (C)0;
+      if (need && ch >= 0) {
+        const int32_t sv = a.xnbr[(int64_t)(i - 1) * a.xstride + crow];
+        int64_t idx;
+        if (PRE) idx = (int64_t)i * a.stride + ((int64_t)sv >= a.vbase ? (int64_t)sv : (int64_t)ch);
+        else idx = sv >= 0 ? (int64_t)i * a.stride + sv : (int64_t)L::S.opp[i] * a.stride + ch;
+        v = Sto<S>::ld(fin, idx, L::S.w[i]);
+        if (DDF) vg = Sto<S>::ld(gin, idx, 0.0);
+        if (!PRE && sv <= -2) v += (C)(2.0 * L::S.w[i] * wall_dot<L>(a.uw, -2 - sv, i) / a.cs2w);
+      }
+      v = group_sum<NCH, C>(v);
+      if (DDF) vg = group_sum<NCH, C>(vg);
+      if (lead && need) {
+        Sto<S>::st(fout, (int64_t)i * a.stride + slot, v / nf, L::S.w[i]);
+        if (DDF) Sto<S>::st(gout, (int64_t)i * a.stride + slot, vg / nf, 0.0);
+      }
+    }
+  } else {
+    // the child's populations as the fine level's next update pulls them
+    // (every child of a coarse ghost has an explicit row), all loads first
+    C f[L::Q], g[DDF ? L::Q : 1];
+    if (ch >= 0)
+      gather_row<L, S, PRE, DDF>(fin, gin, a.xnbr, a.xstride, crow, a.stride, a.vbase, ch, a.uw, a.cs2w, f, g, mask);
 #pragma unroll
-  for (int i = 1; i < L::Q; ++i) {
-    const bool need = (mask >> i) & 1ull;
-    C v = (need && ch >= 0) ? f[i] : (C)0;
-    C vg = (DDF && need && ch >= 0) ? g[i] : (C)0;
-    v = group_sum<NCH, C>(v);
-    if (DDF) vg = group_sum<NCH, C>(vg);
-    if (lead && need) {
-      Sto<S>::st(fout, (int64_t)i * a.stride + slot, v / nf, L::S.w[i]);
-      if (DDF) Sto<S>::st(gout, (int64_t)i * a.stride + slot, vg / nf, 0.0);
+    for (int i = 1; i < L::Q; ++i) {
+      const bool need = (mask >> i) & 1ull;
+      C v = (need && ch >= 0) ? f[i] : (C)0;
+      C vg = (DDF && need && ch >= 0) ? g[i] : (C)0;
+      v = group_sum<NCH, C>(v);
+      if (DDF) vg = group_sum<NCH, C>(vg);
+      if (lead && need) {
+        Sto<S>::st(fout, (int64_t)i * a.stride + slot, v / nf, L::S.w[i]);
+        if (DDF) Sto<S>::st(gout, (int64_t)i * a.stride + slot, vg / nf, 0.0);
+      }
     }
   }
   if (LAM) {
