@@ -111,10 +111,16 @@ __device__ inline void mlp_input_row(__bf16 *xin_row, float rho, float ux, float
   for (int k = 8; k < 16; ++k) xin_row[k] = (__bf16)0.0f;
 }
 
+// Between the layers only the wavefront that owns a tile reads what its
+// lanes wrote to LDS (every caller gives each wavefront its own tile), so
+// waiting for the wavefront's own LDS writes suffices; a block barrier
+// would make the block's wavefronts wait for each other.
+__device__ inline void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 // forward of one 32-sample tile held by one wavefront.  xin [32][16],
 // ha / hb [32][64] scratch, y [32][8] output (normalised), z (optional,
 // training) [3][32][64] pre-activations, h (optional) keeps h1..h3 in
-// ha, hb, hc for the backward pass.  Every thread of the block must call it.
+// ha, hb, hc for the backward pass.
 __device__ inline void mlp_forward_tile(const MlpOperands *P, const __bf16 *xin, __bf16 *h1,
                                         __bf16 *h2, __bf16 *h3, float *y, float *z) {
   const int l = threadIdx.x & 63;
@@ -129,7 +135,7 @@ __device__ inline void mlp_forward_tile(const MlpOperands *P, const __bf16 *xin,
       h1[row * 64 + col] = (__bf16)silu_f(v);
     }
   }
-  __syncthreads();
+  lds_wave_sync();
 #pragma unroll
   for (int n0 = 0; n0 < 64; n0 += 32) {
     const f32x16 acc = gemm_aw<64>(h1, 64, P->w2, 64, n0);
@@ -141,7 +147,7 @@ __device__ inline void mlp_forward_tile(const MlpOperands *P, const __bf16 *xin,
       h2[row * 64 + col] = (__bf16)silu_f(v);
     }
   }
-  __syncthreads();
+  lds_wave_sync();
 #pragma unroll
   for (int n0 = 0; n0 < 64; n0 += 32) {
     const f32x16 acc = gemm_aw<64>(h2, 64, P->w3, 64, n0);
@@ -153,7 +159,7 @@ __device__ inline void mlp_forward_tile(const MlpOperands *P, const __bf16 *xin,
       h3[row * 64 + col] = (__bf16)silu_f(v);
     }
   }
-  __syncthreads();
+  lds_wave_sync();
   {
     const f32x16 acc = gemm_aw<64>(h3, 64, P->w4, 64, 0);
 #pragma unroll
@@ -162,7 +168,7 @@ __device__ inline void mlp_forward_tile(const MlpOperands *P, const __bf16 *xin,
       if (col < 8) y[row * 8 + col] = acc[r] + P->b4[col];
     }
   }
-  __syncthreads();
+  lds_wave_sync();
 }
 
 }  // namespace lbm
