@@ -98,12 +98,14 @@ static int group_of(int lat, const int *v, int *grp) {
   }
   if (cz != 0) return 0;
   static const int q9[][2] = {{0, 0}, {1, 0}, {1, 1}};
+  static const int q13[][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}};
   static const int q21[][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 2}, {3, 0}};
   static const int q37[][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0},
                                {2, 1}, {2, 2}, {3, 0}, {3, 1}};
   const int(*tab)[2];
   int nt;
   if (lat == OL_D2Q9) { tab = q9; nt = 3; }
+  else if (lat == OL_D2Q13) { tab = q13; nt = 4; }
   else if (lat == OL_D2Q21) { tab = q21; nt = 6; }
   else { tab = q37; nt = 8; }
   for (int k = 0; k < nt; ++k)
@@ -205,9 +207,9 @@ static int cmp_vel(const void *pa, const void *pb) {
 
 static int setup_lattice(ol_sim *s) {
   int lat = s->p.lattice;
-  if (lat < 0 || lat > 3) return fail(s, -1, "unknown lattice %d", lat);
+  if (lat < 0 || lat > 4) return fail(s, -1, "unknown lattice %d", lat);
   s->D = (lat == OL_D3Q27) ? 3 : 2;
-  int R = (lat == OL_D2Q21 || lat == OL_D2Q37) ? 3 : 1;
+  int R = (lat == OL_D2Q21 || lat == OL_D2Q37) ? 3 : lat == OL_D2Q13 ? 2 : 1;
   int vel[MAXQ][3], nq = 0;
   for (int z = (s->D == 3 ? -R : 0); z <= (s->D == 3 ? R : 0); ++z)
     for (int y = -R; y <= R; ++y)
@@ -235,6 +237,11 @@ static int setup_lattice(ol_sim *s) {
       s->w[i] = w9[g];
       break;
     }
+    case OL_D2Q13: {
+      static const double w13[4] = {36.0 / 96.0, 8.0 / 96.0, 6.0 / 96.0, 1.0 / 96.0};
+      s->w[i] = w13[g];
+      break;
+    }
     case OL_D2Q21: {
       static const double w21[6] = {91.0 / 324.0, 1.0 / 12.0, 2.0 / 27.0,
                                     7.0 / 360.0, 1.0 / 432.0, 1.0 / 1620.0};
@@ -252,6 +259,7 @@ static int setup_lattice(ol_sim *s) {
   }
   s->cs2 = lat == OL_D2Q9 || lat == OL_D3Q27 ? 1.0 / 3.0
            : lat == OL_D2Q21                  ? 2.0 / 3.0
+           : lat == OL_D2Q13                  ? 0.5
                                               : (double)cs37;
   for (int i = 0; i < nq; ++i)
     for (int j = 0; j < nq; ++j)
@@ -632,7 +640,7 @@ ol_sim *ol_create(const ol_params *p) {
   int lat = p->lattice, coll = p->collision;
   int ok = ((lat == OL_D2Q9 || lat == OL_D3Q27) && (coll == OL_BGK || coll == OL_RR)) ||
            (lat == OL_D2Q37 && coll == OL_DDF_POLY) ||
-           (lat == OL_D2Q21 && coll == OL_DDF_NEWTON);
+           ((lat == OL_D2Q21 || lat == OL_D2Q13) && coll == OL_DDF_NEWTON);
   if (!ok) { free(s); return NULL; }
   return s;
 }

@@ -20,7 +20,7 @@
 extern "C" {
 #endif
 
-enum { OL_D2Q9 = 0, OL_D3Q27 = 1, OL_D2Q21 = 2, OL_D2Q37 = 3 };
+enum { OL_D2Q9 = 0, OL_D3Q27 = 1, OL_D2Q21 = 2, OL_D2Q37 = 3, OL_D2Q13 = 4 };
 enum { OL_BGK = 0, OL_RR = 1, OL_DDF_POLY = 2, OL_DDF_NEWTON = 3 };
 enum { OL_BC_PERIODIC = 0, OL_BC_WALL = 1, OL_BC_MOVING_WALL = 2,
        OL_BC_NEUMANN = 3, OL_BC_EQUILIBRIUM = 4 };

@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-LATTICES = {"D2Q9": 0, "D3Q27": 1, "D2Q21": 2, "D2Q37": 3}
+LATTICES = {"D2Q9": 0, "D3Q27": 1, "D2Q21": 2, "D2Q37": 3, "D2Q13": 4}
 COLLISIONS = {"BGK": 0, "RR": 1, "DDF_POLY": 2, "DDF_NEWTON": 3}
 BC_KINDS = {"periodic": 0, "wall": 1, "moving_wall": 2, "neumann": 3, "equilibrium": 4}
 NONE, SOLID = -1, -2

@@ -227,9 +227,17 @@ def newton_residual(o, u, T, lam):
     return mvec @ f - M
 
 
-def test_newton_solves_constraints_and_symmetries():
-    o = Oracle("D2Q21", "DDF_NEWTON", T0=0.65, gamma=1.4)
-    for u, T in [((0.3, -0.2), 0.65), ((1.43, 0.0), 0.65), ((0.0, 0.0), 0.9), ((0.5, 0.7), 0.5)]:
+NEWTON_STATES = {
+    "D2Q21": (0.65, [((0.3, -0.2), 0.65), ((1.43, 0.0), 0.65), ((0.0, 0.0), 0.9), ((0.5, 0.7), 0.5)]),
+    "D2Q13": (0.35, [((0.3, -0.2), 0.35), ((0.8, 0.0), 0.35), ((0.0, 0.0), 0.5), ((0.3, 0.4), 0.3)]),
+}
+
+
+@pytest.mark.parametrize("name", list(NEWTON_STATES))
+def test_newton_solves_constraints_and_symmetries(name):
+    T0, states = NEWTON_STATES[name]
+    o = Oracle(name, "DDF_NEWTON", T0=T0, gamma=1.4)
+    for u, T in states:
         it, lam = o.newton(u, T)
         assert it >= 0
         assert np.max(np.abs(newton_residual(o, u, T, lam))) <= 1e-12

@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # highest degree of monomials integrated exactly)
 SPEC = {
     "D2Q9": ("BGK", {(0, 0): 1, (1, 0): 4, (1, 1): 4}, 5),
+    "D2Q13": ("DDF_NEWTON", {(0, 0): 1, (1, 0): 4, (1, 1): 4, (2, 0): 4}, 5),
     "D2Q21": ("DDF_NEWTON", {(0, 0): 1, (1, 0): 4, (1, 1): 4, (2, 0): 4, (2, 2): 4, (3, 0): 4}, 7),
     "D2Q37": ("DDF_POLY", {(0, 0): 1, (1, 0): 4, (1, 1): 4, (2, 0): 4, (2, 1): 8, (2, 2): 4,
                            (3, 0): 4, (3, 1): 8}, 9),
@@ -26,6 +27,7 @@ SPEC = {
 # D1Q3 weights 2/3, 1/6, 1/6)
 PRINTED = {
     "D2Q9": ({(0, 0): Fr(4, 9), (1, 0): Fr(1, 9), (1, 1): Fr(1, 36)}, Fr(1, 3)),
+    "D2Q13": ({(0, 0): Fr(36, 96), (1, 0): Fr(8, 96), (1, 1): Fr(6, 96), (2, 0): Fr(1, 96)}, Fr(1, 2)),
     "D2Q21": ({(0, 0): Fr(91, 324), (1, 0): Fr(1, 12), (1, 1): Fr(2, 27), (2, 0): Fr(7, 360),
                (2, 2): Fr(1, 432), (3, 0): Fr(1, 1620)}, Fr(2, 3)),
 }
@@ -68,7 +70,7 @@ def test_velocity_set_and_order(name):
     assert o.B == int(np.abs(c).max())
 
 
-@pytest.mark.parametrize("name", ["D2Q9", "D2Q21"])
+@pytest.mark.parametrize("name", ["D2Q9", "D2Q13", "D2Q21"])
 def test_printed_rational_weights(name):
     o = lattice(name)
     wt, cs2 = PRINTED[name]
@@ -118,3 +120,12 @@ def test_isotropy_moments(name):
         lhs = float((o.w * mono).sum())
         rhs = float(np.prod([gauss_moment(p, o.cs2) for p in powers]))
         assert abs(lhs - rhs) < 2e-14 * max(1.0, abs(rhs)), (powers, lhs, rhs)
+
+
+def test_d2q13_not_isotropic_at_sixth_order():
+    """the degree of D2Q13 is exactly five: its sixth moments miss the
+    Gaussian's (sum w xi_x^6 = 168/96 against 15 cs2^3 = 180/96)"""
+    o = lattice("D2Q13")
+    x = o.c[:, 0].astype(np.float64)
+    assert abs((o.w * x ** 6).sum() - 168.0 / 96.0) < 1e-14
+    assert abs((o.w * x ** 6).sum() - 15.0 * o.cs2 ** 3) > 0.1
