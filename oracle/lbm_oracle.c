@@ -267,7 +267,8 @@ static int setup_lattice(ol_sim *s) {
           s->c[j][2] == -s->c[i][2])
         s->opp[i] = j;
   /* kept Hermite multi-indices (Table lattices_hermite; product basis for
-   * D3Q27; full fourth order for the D2Q37 thermal equilibrium) */
+   * D3Q27; full third order for D2Q13 and D2Q21, App. A.2; full fourth
+   * order for the D2Q37 thermal equilibrium) */
   s->nm = 0;
   for (int mz = 0; mz <= 4; ++mz)
     for (int my = 0; my <= 4; ++my)
@@ -276,7 +277,7 @@ static int setup_lattice(ol_sim *s) {
         if (lat == OL_D2Q9) keep = mz == 0 && mx <= 2 && my <= 2;
         else if (lat == OL_D3Q27) keep = mx <= 2 && my <= 2 && mz <= 2;
         else if (lat == OL_D2Q37) keep = mz == 0 && mx + my <= 4;
-        else keep = 0;
+        else keep = mz == 0 && mx + my <= 3; /* D2Q13, D2Q21 */
         if (!keep) continue;
         s->m[s->nm][0] = mx; s->m[s->nm][1] = my; s->m[s->nm][2] = mz;
         s->nm++;
@@ -638,7 +639,7 @@ ol_sim *ol_create(const ol_params *p) {
   s->p = *p;
   if (setup_lattice(s) != 0) { free(s); return NULL; }
   int lat = p->lattice, coll = p->collision;
-  int ok = ((lat == OL_D2Q9 || lat == OL_D3Q27) && (coll == OL_BGK || coll == OL_RR)) ||
+  int ok = (lat != OL_D2Q37 && (coll == OL_BGK || coll == OL_RR)) ||
            (lat == OL_D2Q37 && coll == OL_DDF_POLY) ||
            ((lat == OL_D2Q21 || lat == OL_D2Q13) && coll == OL_DDF_NEWTON);
   if (!ok) { free(s); return NULL; }

@@ -3,6 +3,7 @@ closed forms, moment identities, the paper's printed fourth-order
 non-equilibrium recursion, the DDF closure, the kinetic sensor table and the
 Newton constraint residual."""
 import itertools
+import math
 
 import numpy as np
 import pytest
@@ -164,7 +165,7 @@ def test_rr_d3q27_pair_sum_closed_form():
             assert abs(got - (aeq + (1 - 1 / tau) * an)) < 2e-15, m
 
 
-@pytest.mark.parametrize("name", ["D2Q9", "D3Q27"])
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q27", "D2Q13", "D2Q21"])
 @pytest.mark.parametrize("coll", ["BGK", "RR"])
 def test_collision_conserves_and_fixes_equilibrium(name, coll):
     o = Oracle(name, coll, nu_finest=0.1)
@@ -179,6 +180,52 @@ def test_collision_conserves_and_fixes_equilibrium(name, coll):
     assert np.max(np.abs(fs2 - fe)) < 1e-15
     fs1, _, _, _ = o.collide(1.0, f)  # tau = 1: full relaxation
     assert np.max(np.abs(fs1 - fe)) < 1e-15
+
+
+@pytest.mark.parametrize("name", ["D2Q13", "D2Q21"])
+def test_rr_third_order_lattices_by_least_squares(name):
+    """D2Q13 and D2Q21 expand to full third order and no further (Table
+    lattices_hermite, App. A.2).  The Hermite coefficients of a
+    post-collision state are recovered by least squares on the basis
+    w_i H_m(xi_i), |m| <= 3 (13 or 21 equations, 10 unknowns): the state must
+    lie in that span, and the coefficients must be the equilibrium moments
+    rho u^m plus (1 - 1/tau) times the printed non-equilibrium forms, with
+    a^(2)_neq taken from the raw second moment of the populations (a route
+    the oracle does not take: it projects f - f_eq)."""
+    o = Oracle(name, "RR", nu_finest=0.1)
+    cs2 = o.cs2
+    h = [lambda x: 1.0 + 0 * x, lambda x: x, lambda x: x * x - cs2, lambda x: (x * x - 3 * cs2) * x]
+    xi = o.c[:, :2].astype(float)
+    ms = [(mx, n - mx) for n in range(4) for mx in range(n, -1, -1)]
+    A = np.stack([o.w * h[mx](xi[:, 0]) * h[my](xi[:, 1]) for mx, my in ms], axis=1)
+    assert np.linalg.matrix_rank(A) == len(ms)
+    tau = 0.77
+    k = 1.0 - 1.0 / tau
+    for _ in range(4):
+        f, fs = rr_case(o, tau)
+        rho = f.sum()
+        ux, uy = xi.T @ f / rho
+        P = np.einsum("i,ia,ib->ab", f, xi, xi)
+        axx = P[0, 0] - rho * ux * ux - rho * cs2
+        axy = P[0, 1] - rho * ux * uy
+        ayy = P[1, 1] - rho * uy * uy - rho * cs2
+        an = {(2, 0): axx, (1, 1): axy, (0, 2): ayy,
+              (3, 0): 3 * ux * axx, (2, 1): 2 * ux * axy + uy * axx,
+              (1, 2): 2 * uy * axy + ux * ayy, (0, 3): 3 * uy * ayy}
+        b, *_ = np.linalg.lstsq(A, fs, rcond=None)
+        assert np.max(np.abs(A @ b - fs)) < 1e-15
+        for j, (mx, my) in enumerate(ms):
+            n = mx + my
+            got = b[j] * math.factorial(mx) * math.factorial(my) * cs2 ** n
+            want = rho * ux ** mx * uy ** my + k * an.get((mx, my), 0.0)
+            assert abs(got - want) < 1e-14, ((mx, my), got, want)
+        # the equilibrium alone: coefficients rho u^m
+        fe, _, _ = o.feq(rho, (ux, uy))
+        b, *_ = np.linalg.lstsq(A, fe, rcond=None)
+        assert np.max(np.abs(A @ b - fe)) < 1e-15
+        for j, (mx, my) in enumerate(ms):
+            got = b[j] * math.factorial(mx) * math.factorial(my) * cs2 ** (mx + my)
+            assert abs(got - rho * ux ** mx * uy ** my) < 1e-14
 
 
 def test_bgk_relaxation():
