@@ -11,7 +11,7 @@
 
 namespace lbm {
 
-enum LatticeKind { LAT_D2Q9 = 0, LAT_D3Q27 = 1, LAT_D2Q21 = 2, LAT_D2Q37 = 3 };
+enum LatticeKind { LAT_D2Q9 = 0, LAT_D3Q27 = 1, LAT_D2Q21 = 2, LAT_D2Q37 = 3, LAT_D2Q13 = 4 };
 
 struct Vel {
   int x, y, z;
@@ -42,6 +42,13 @@ constexpr double weight_of(int kind, int x, int y, int z) {
     if (hi == 0) return 4.0 / 9.0;
     if (hi == 1 && lo == 0) return 1.0 / 9.0;
     if (hi == 1 && lo == 1) return 1.0 / 36.0;
+    return 0.0;
+  }
+  if (kind == LAT_D2Q13) {
+    if (hi == 0) return 36.0 / 96.0;
+    if (hi == 1 && lo == 0) return 8.0 / 96.0;
+    if (hi == 1 && lo == 1) return 6.0 / 96.0;
+    if (hi == 2 && lo == 0) return 1.0 / 96.0;
     return 0.0;
   }
   if (kind == LAT_D2Q21) {
@@ -121,6 +128,13 @@ struct Lattice<LAT_D3Q27> {
 };
 
 template <>
+struct Lattice<LAT_D2Q13> {
+  static constexpr int kind = LAT_D2Q13, D = 2, Q = 13, B = 2;
+  static constexpr double cs2 = 0.5;
+  static constexpr VelSet<13> S = make_set<LAT_D2Q13, 13, 2, 2>();
+};
+
+template <>
 struct Lattice<LAT_D2Q21> {
   static constexpr int kind = LAT_D2Q21, D = 2, Q = 21, B = 3;
   static constexpr double cs2 = 2.0 / 3.0;
@@ -168,6 +182,7 @@ inline bool get_lattice_info(int kind, LatticeInfo *out) {
     case LAT_D3Q27: *out = lattice_info<LAT_D3Q27>(); return true;
     case LAT_D2Q21: *out = lattice_info<LAT_D2Q21>(); return true;
     case LAT_D2Q37: *out = lattice_info<LAT_D2Q37>(); return true;
+    case LAT_D2Q13: *out = lattice_info<LAT_D2Q13>(); return true;
     default: return false;
   }
 }

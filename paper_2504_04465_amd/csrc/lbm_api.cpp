@@ -447,6 +447,7 @@ lbm_status lbm_create(const lbm_params *params, lbm_dev_alloc_fn dev_alloc_fn,
     case LBM_D3Q27: ok = get_ops_d3q27(coll, sto, &c->ops); break;
     case LBM_D2Q21: ok = get_ops_d2q21(coll, sto, &c->ops); break;
     case LBM_D2Q37: ok = get_ops_d2q37(coll, sto, &c->ops); break;
+    case LBM_D2Q13: ok = get_ops_d2q13(coll, sto, &c->ops); break;
   }
   if (!ok) {
     delete c;

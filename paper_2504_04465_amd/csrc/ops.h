@@ -163,5 +163,6 @@ bool get_ops_d2q9(int coll, int storage, Ops *out);
 bool get_ops_d3q27(int coll, int storage, Ops *out);
 bool get_ops_d2q21(int coll, int storage, Ops *out);
 bool get_ops_d2q37(int coll, int storage, Ops *out);
+bool get_ops_d2q13(int coll, int storage, Ops *out);
 
 }  // namespace lbm

@@ -17,7 +17,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 # LBM_LIB_PATH selects another build of the same library (e.g. a tuning variant)
 LIB_PATH = os.environ.get("LBM_LIB_PATH", os.path.join(PKG, "liblbm.so"))
 
-LATTICES = {"D2Q9": 0, "D3Q27": 1, "D2Q21": 2, "D2Q37": 3}
+LATTICES = {"D2Q9": 0, "D3Q27": 1, "D2Q21": 2, "D2Q37": 3, "D2Q13": 4}
 COLLISIONS = {"BGK": 0, "RR": 1, "DDF_POLY": 2, "DDF_NEWTON": 3, "DDF_MLP": 4, "DDF_MLP_NEWTON": 5}
 STORAGE = {"fp64": 0, "fp32": 1, "fp16": 2}
 BC_KINDS = {"periodic": 0, "wall": 1, "moving_wall": 2, "neumann": 3, "equilibrium": 4}
@@ -259,7 +259,7 @@ class LBM:
         eq = C.c_double()
         self._check(self._L.lbm_grid_info(self.h, C.byref(n), _ptr(npl), C.byref(ng), C.byref(eq)))
         self.n, self.n_per_level, self.n_ghosts, self.eq_fine = n.value, npl[:n_levels].copy(), ng.value, eq.value
-        self.Q = {"D2Q9": 9, "D3Q27": 27, "D2Q21": 21, "D2Q37": 37}[self.lattice]
+        self.Q = {"D2Q9": 9, "D3Q27": 27, "D2Q21": 21, "D2Q37": 37, "D2Q13": 13}[self.lattice]
         self.n_mom = 1 + dim + (1 if self.ddf else 0)
 
     def layout(self):

@@ -325,11 +325,12 @@ def airfoil(scale: int = 1, steps: int = 1000, Ma: float = 1.5, Ma0: float = 1.0
 # --------------------------------------------------------------------------
 def shear(n: int = 32, levels: int = 2, lattice: str = "D2Q9", collision: str = "BGK",
           nu_finest: float = 0.02, steps: int = 10, kind: str = "dsl", u0: float = 0.05,
-          band=None, seed: int = 7, storage: str = "fp64") -> Workload:
+          band=None, seed: int = 7, storage: str = "fp64", T0: float = 1.0) -> Workload:
     """Periodic box.  kind="dsl": double shear layer of the paper's Sec. 5.1
     with a horizontal refinement band; kind="wave": decaying sinusoidal shear
     wave; kind="random": random smooth-ish perturbation.  `band` gives the
-    refined rows of each level as fractions of n (nested)."""
+    refined rows of each level as fractions of n (nested).  Double
+    distribution lattices start at the uniform temperature T0."""
     dim = 3 if lattice == "D3Q27" else 2
     ext = (n, n, n) if dim == 3 else (n, n)
     if band is None:
@@ -362,11 +363,11 @@ def shear(n: int = 32, levels: int = 2, lattice: str = "D2Q9", collision: str = 
             for d in range(dim):
                 m[1 + d] = uniform_noise(seed, ids, d, u0)
         if ddf:
-            m[-1] = 1.0
+            m[-1] = T0
         return m
 
     return Workload("shear", lattice, collision, dim, ext, levels, refine,
-                    [None] * levels, faces, nu_finest, steps, T0=1.0, init=init,
+                    [None] * levels, faces, nu_finest, steps, T0=T0, init=init,
                     storage=storage)
 
 

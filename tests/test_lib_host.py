@@ -46,6 +46,8 @@ def cases():
     w.refine[0].data[:] = m[4:20, 0:22]
     w.faces = [W.Face("wall"), W.Face("wall"), W.Face("periodic"), W.Face("periodic"), W.Face(), W.Face()]
     out.append(("blob", w))
+    # two ghost layers at the interfaces (largest velocity component 2)
+    out.append(("shear_q13", W.shear(n=32, levels=3, lattice="D2Q13", collision="DDF_NEWTON", T0=0.35)))
     return out + edge_cases()
 
 
@@ -97,6 +99,8 @@ def test_unsupported_combinations_rejected():
     assert e.value.code == -7
     with pytest.raises(B.LbmError):
         B.LBM("D2Q21", "DDF_NEWTON", "fp16", host_only=True)
+    with pytest.raises(B.LbmError):
+        B.LBM("D2Q13", "DDF_POLY", "fp32", host_only=True)
 
 
 def test_equivalent_fine_cells_paper_table():
