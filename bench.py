@@ -27,7 +27,20 @@ METRIC = "MLUPS + % HBM peak; surrogate vs Newton equilibrium speedup at rel-L2â
 HBM_PEAK_GBS = 8000.0
 
 
-def workload(name, scale, storage):
+# the paper's A100 throughputs (MLUPS) for the same workloads: tree
+# (neighbour-list) RR on the uniform L = 2^13 cavity (Table
+# perfo_loss_neighbor_list_rr), DDF numerical equilibrium on the uniform
+# L = 2^13 Sod tube (Table perfo_fully_gpu_and_speedup, single precision)
+PAPER_A100_MLUPS = {
+    ("cavity_uniform", "D2Q9", "fp32"): 10541.0, ("cavity_uniform", "D2Q9", "fp64"): 7041.0,
+    ("cavity_uniform", "D2Q13", "fp32"): 5634.0, ("cavity_uniform", "D2Q13", "fp64"): 3452.0,
+    ("cavity_uniform", "D2Q21", "fp32"): 3405.0, ("cavity_uniform", "D2Q21", "fp64"): 2140.0,
+    ("sod_newton", "D2Q13", "fp32"): 1259.1, ("sod_newton", "D2Q21", "fp32"): 618.5,
+}
+SOD_T0 = {"D2Q13": 0.35, "D2Q21": 0.9}
+
+
+def workload(name, scale, storage, lattice=None):
     from paper_2504_04465_amd import workloads as W
     if name == "sphere":
         return W.sphere(scale=scale, storage=storage or "fp32")
@@ -39,6 +52,15 @@ def workload(name, scale, storage):
         return W.sod(nx=4096 // scale, storage=storage or "fp32")
     if name == "airfoil":
         return W.airfoil(scale=scale, storage=storage or "fp32")
+    if name == "cavity_uniform":
+        # uniform L = 2^13 lid-driven cavity, RR
+        return W.cavity(n=8192 // scale, levels=1, Re=1000.0, lattice=lattice or "D2Q13", collision="RR",
+                        storage=storage or "fp32")
+    if name == "sod_newton":
+        # uniform L x L Sod tube, L = 2^13, DDF numerical equilibrium
+        lat = lattice or "D2Q13"
+        return W.sod(nx=8192 // scale, ny=8192 // scale, band=False, lattice=lat, collision="DDF_NEWTON",
+                     theta=SOD_T0[lat], theta_at="right", storage=storage or "fp32")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -58,6 +80,8 @@ def cpu_baseline(args):
     env = dict(os.environ, OMP_NUM_THREADS=str(threads))
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", "--workload", args.workload,
            "--cpu-scale", str(args.cpu_scale), "--cpu-steps", str(args.cpu_steps)]
+    if args.lattice:
+        cmd += ["--lattice", args.lattice]
     r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
     if r.returncode != 0:
         return {"value": None, "unit": "MLUPS", "cores": threads, "kind": "oracle",
@@ -69,7 +93,7 @@ def cpu_baseline(args):
 
 def cpu_baseline_child(args):
     from oracle.oracle import Oracle
-    w = workload(args.workload, args.cpu_scale, None)
+    w = workload(args.workload, args.cpu_scale, None, args.lattice)
     o = Oracle.from_workload(w)
     o.init_workload(w)
     npl = o.level_counts()
@@ -286,6 +310,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="sphere")
     ap.add_argument("--storage", default=None)
+    ap.add_argument("--lattice", default=None, help="lattice of the cavity_uniform / sod_newton workloads")
     ap.add_argument("--scale", type=int, default=1)
     ap.add_argument("--cpu-scale", type=int, default=4)
     ap.add_argument("--cpu-steps", type=int, default=60)
@@ -318,7 +343,7 @@ def main():
     import torch
     from paper_2504_04465_amd import lbm as B
 
-    w = workload(args.workload, args.scale, args.storage)
+    w = workload(args.workload, args.scale, args.storage, args.lattice)
     storage = args.storage or w.storage
     t0 = time.perf_counter()
     s = B.LBM.from_workload(w, storage=storage)
@@ -393,7 +418,8 @@ def main():
         "ms_per_step": round((dt_graph if dt_graph is not None else dt) / args.steps * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
-        "vs_baseline": None,
+        "vs_baseline": (round(mlups / PAPER_A100_MLUPS[(args.workload, w.lattice, storage)], 3)
+                        if args.scale == 1 and (args.workload, w.lattice, storage) in PAPER_A100_MLUPS else None),
         "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f16-storage/f32-compute"}[storage],
         "data": "synthetic",
         "config": {"workload": describe(w, storage), "cells": int(s.n),
@@ -410,6 +436,7 @@ def main():
         "modeled_hbm_frac_whole_step": round(per_step * bpu_f * args.steps / dt / 1e9 / HBM_PEAK_GBS, 4),
         "mlups_paper_formula": round(s.n * args.steps * (1 << (L - 1)) / (dt_graph or dt) / 1e6, 2),
         "launch": "HIP graph per pair of coarse steps" if dt_graph is not None else "kernel launches",
+        "paper_a100_mlups": PAPER_A100_MLUPS.get((args.workload, w.lattice, storage)) if args.scale == 1 else None,
         "newton": {"calls": st["newton_calls"], "iterations": st["newton_iterations"],
                    "failures": st["newton_failures"]},
     }

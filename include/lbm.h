@@ -55,6 +55,8 @@ enum { LBM_D2Q9 = 0, LBM_D3Q27 = 1, LBM_D2Q21 = 2, LBM_D2Q37 = 3, LBM_D2Q13 = 4 
 /* collision models of App. A.2:
  *   BGK            Eq. CollisionStep with the polynomial equilibrium Eq. GenEq
  *   RR             recursive regularisation, Eq. GenRegCollision
+ *                  (BGK and RR: D2Q9 and D3Q27 on the product basis, D2Q13
+ *                  and D2Q21 on the full third-order basis; all storages)
  *   DDF_POLY       double distribution, fourth-order thermal polynomial
  *                  equilibrium, g_eq of Eq. gEq, BGK on f and g (D2Q37)
  *   DDF_NEWTON     double distribution, numerical equilibrium Eq. exponential

@@ -1,7 +1,8 @@
 // Kernel instantiations for D2Q21: double distribution with the numerical
 // (entropy-maximising) equilibrium solved by Newton, or predicted by the
 // multiplier surrogate (alone, or with one Newton correction and a Newton
-// fallback); FP64 / FP32 storage.
+// fallback), FP64 / FP32 storage; BGK and recursive regularisation on the
+// full third-order Hermite basis, FP64 / FP32 / FP16 storage.
 #include "kernels.cuh"
 #include "mlp.cuh"
 
@@ -141,6 +142,15 @@ struct LaunchMlp {
 };
 
 bool get_ops_d2q21(int coll, int storage, Ops *out) {
+  // weakly compressible: BGK / recursive regularisation on the full
+  // third-order Hermite basis
+  if (coll == COLL_BGK || coll == COLL_RR) {
+    const bool rr = coll == COLL_RR;
+    if (storage == STO_FP64) { *out = rr ? Launch<L21, COLL_RR, double>::ops() : Launch<L21, COLL_BGK, double>::ops(); return true; }
+    if (storage == STO_FP32) { *out = rr ? Launch<L21, COLL_RR, float>::ops() : Launch<L21, COLL_BGK, float>::ops(); return true; }
+    if (storage == STO_FP16) { *out = rr ? Launch<L21, COLL_RR, __half>::ops() : Launch<L21, COLL_BGK, __half>::ops(); return true; }
+    return false;
+  }
   if (storage != STO_FP64 && storage != STO_FP32) return false;
   const bool f64 = storage == STO_FP64;
   switch (coll) {

@@ -465,6 +465,96 @@ __device__ inline void equilibrium_thermal(C rho, const C *u, C T, C *feq) {
 }
 
 // ---------------------------------------------------------------------------
+// third-order lattices (D2Q13, D2Q21): equilibrium and recursive
+// regularisation on the full Hermite basis up to third order, the ten
+// tensors (mx, my) with mx + my <= 3 and none of fourth order (App. A.2)
+// ---------------------------------------------------------------------------
+template <class L>
+constexpr bool product_basis() {
+  return L::kind == LAT_D2Q9 || L::kind == LAT_D3Q27;
+}
+
+template <int Q>
+struct Hermite3Table {
+  int mx[10], my[10];
+  double hw[Q][10];  // w_i H_m(xi_i) / (mx! my! cs2^(mx + my))
+};
+
+template <class L>
+constexpr Hermite3Table<L::Q> make_hermite3() {
+  Hermite3Table<L::Q> t{};
+  int k = 0;
+  for (int n = 0; n <= 3; ++n)
+    for (int my = 0; my <= n; ++my) {
+      t.mx[k] = n - my;
+      t.my[k] = my;
+      ++k;
+    }
+  for (int i = 0; i < L::Q; ++i)
+    for (int k2 = 0; k2 < 10; ++k2) {
+      const int a = t.mx[k2], b = t.my[k2];
+      t.hw[i][k2] = L::S.w[i] * h1c(a, L::S.v[i].x, L::cs2) * h1c(b, L::S.v[i].y, L::cs2) /
+                    (fact_c(a) * fact_c(b) * pow_c(L::cs2, a + b));
+    }
+  return t;
+}
+
+template <class L>
+struct Hermite3 {
+  static constexpr Hermite3Table<L::Q> T = make_hermite3<L>();
+};
+
+// f_i = sum_m hw_im b_m
+template <class L, class C>
+__device__ inline void hermite3_expand(const C (&b)[10], C *f) {
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    C v = (C)0;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+      const double h = Hermite3<L>::T.hw[i][k];
+      if (h != 0.0) v += (C)h * b[k];
+    }
+    f[i] = v;
+  }
+}
+
+template <class L, class C>
+__device__ inline void equilibrium_hermite3(C rho, const C *u, C *feq) {
+  const C px[4] = {(C)1, u[0], u[0] * u[0], u[0] * u[0] * u[0]};
+  const C py[4] = {(C)1, u[1], u[1] * u[1], u[1] * u[1] * u[1]};
+  C b[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) b[k] = rho * px[Hermite3<L>::T.mx[k]] * py[Hermite3<L>::T.my[k]];
+  hermite3_expand<L, C>(b, feq);
+}
+
+// b_m = rhop u^m + k a_neq,m with a^(2)_neq = P - rho u u - rho cs2 I and
+// the third-order a_neq from the non-equilibrium recursion (pair sums:
+// xxx = 3 u_x a_xx, xxy = 2 u_x a_xy + u_y a_xx, and their mirrors)
+template <class L, class C>
+__device__ inline void rr_hermite3(C *f, C rho, C rhop, const C *u, const C (&P)[3][3], C k, bool trace_eq) {
+  constexpr C cs2 = (C)L::cs2;
+  const C ux = u[0], uy = u[1];
+  C axx = P[0][0] - rho * ux * ux - rho * cs2;
+  const C axy = P[0][1] - rho * ux * uy;
+  C ayy = P[1][1] - rho * uy * uy - rho * cs2;
+  if (trace_eq) {
+    const C h = (C)0.5 * (axx + ayy);
+    axx -= h;
+    ayy -= h;
+  }
+  const C an[10] = {(C)0, (C)0, (C)0, axx, axy, ayy, (C)3 * ux * axx, (C)2 * ux * axy + uy * axx,
+                    (C)2 * uy * axy + ux * ayy, (C)3 * uy * ayy};
+  const C px[4] = {(C)1, ux, ux * ux, ux * ux * ux};
+  const C py[4] = {(C)1, uy, uy * uy, uy * uy * uy};
+  C b[10];
+#pragma unroll
+  for (int m = 0; m < 10; ++m) b[m] = rhop * px[Hermite3<L>::T.mx[m]] * py[Hermite3<L>::T.my[m]] + k * an[m];
+  hermite3_expand<L, C>(b, f);
+}
+
+// ---------------------------------------------------------------------------
 // numerical (entropy-maximising) equilibrium, D2Q21: f_eq = rho exp(-(1 +
 // lambda . m_i)) under the eight moment constraints; Newton with a Cholesky
 // step and backtracking on ||G||_2, FP64
@@ -769,7 +859,8 @@ __device__ inline int equilibrium_any(C rho, const C *u, C T, const PhysArgs &ph
                                       bool warm, C *feq, C *geq) {
   int it = 0;
   if constexpr (COLL == COLL_BGK || COLL == COLL_RR) {
-    equilibrium_product<L, C>(rho, u, feq);
+    if constexpr (product_basis<L>()) equilibrium_product<L, C>(rho, u, feq);
+    else equilibrium_hermite3<L, C>(rho, u, feq);
   } else if constexpr (COLL == COLL_DDF_POLY) {
     equilibrium_thermal<L, C>(rho, u, T, feq);
   } else {
@@ -850,7 +941,8 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
     if (!(rho > (C)0) || !isfinite(rho)) count_add(a.counters, CNT_NONFINITE, 1);
     if constexpr (COLL == COLL_BGK) {
       C feq[Q];
-      equilibrium_product<L, C>(rhop, u, feq);
+      if constexpr (product_basis<L>()) equilibrium_product<L, C>(rhop, u, feq);
+      else equilibrium_hermite3<L, C>(rhop, u, feq);
       const C om = (C)(1.0 / a.ph.tau);
 #pragma unroll
       for (int i = 0; i < Q; ++i) f[i] = f[i] - om * (f[i] - feq[i]);
@@ -873,7 +965,10 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
       for (int x = 0; x < L::D; ++x)
 #pragma unroll
         for (int y = 0; y < x; ++y) P[x][y] = P[y][x];
-      rr_product<L, C>(f, rho, rhop, u, P, (C)(1.0 - 1.0 / a.ph.tau), a.ph.trace_eq != 0);
+      if constexpr (product_basis<L>())
+        rr_product<L, C>(f, rho, rhop, u, P, (C)(1.0 - 1.0 / a.ph.tau), a.ph.trace_eq != 0);
+      else
+        rr_hermite3<L, C>(f, rho, rhop, u, P, (C)(1.0 - 1.0 / a.ph.tau), a.ph.trace_eq != 0);
     } else {
       C feq[Q], geq[Q];
       double lam[NLAM];

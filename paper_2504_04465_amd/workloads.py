@@ -148,10 +148,13 @@ def _centre_coords(coords, level):
 
 
 # --------------------------------------------------------------------------
-# lid-driven cavity: D2Q9 BGK, two levels, top quarter refined
+# lid-driven cavity: D2Q9 BGK, two levels, top quarter refined (or one
+# level and any weakly compressible lattice / collision, Sec. 5.2 and the
+# uniform-grid performance runs)
 # --------------------------------------------------------------------------
 def cavity(n: int = 64, steps: int = 1000, lid: float = 0.1, Re: float = 100.0,
-           refined_rows: Optional[int] = None, levels: int = 2) -> Workload:
+           refined_rows: Optional[int] = None, levels: int = 2, lattice: str = "D2Q9",
+           collision: str = "BGK", storage: str = "fp64") -> Workload:
     dim, ext = 2, (n, n)
     rr = n // 4 if refined_rows is None else refined_rows
     refine = []
@@ -167,8 +170,8 @@ def cavity(n: int = 64, steps: int = 1000, lid: float = 0.1, Re: float = 100.0,
         m[0] = 1.0
         return m
 
-    return Workload("cavity", "D2Q9", "BGK", dim, ext, levels, refine,
-                    [None] * levels, faces, nu_f, steps, init=init, storage="fp64")
+    return Workload("cavity", lattice, collision, dim, ext, levels, refine,
+                    [None] * levels, faces, nu_f, steps, init=init, storage=storage)
 
 
 # --------------------------------------------------------------------------
@@ -240,10 +243,15 @@ def sphere(scale: int = 1, steps: int = 500, seed: int = 3, Ma: float = 0.1,
 
 
 # --------------------------------------------------------------------------
-# Sod shock tube: D2Q37 DDF polynomial equilibrium, refined band
+# Sod shock tube: D2Q37 DDF polynomial equilibrium, refined band (or any
+# double-distribution lattice / equilibrium of the paper's Sec. 6.1)
 # --------------------------------------------------------------------------
 def sod(nx: int = 4096, ny: int = 8, steps: Optional[int] = None, theta: float = 0.65,
-        sensor_A: float = 1.5, storage: str = "fp32", band: bool = True) -> Workload:
+        sensor_A: float = 1.5, storage: str = "fp32", band: bool = True,
+        lattice: str = "D2Q37", collision: str = "DDF_POLY", theta_at: str = "left") -> Workload:
+    """(p, rho) = (1, 1) left and (0.1, 0.125) right, the paper's ratios;
+    T = theta p / rho scaled so that the state named by theta_at ("left"
+    or "right", the paper's reference state) has temperature theta."""
     dim, ext = 2, (nx, ny)
     L = 2 if band else 1
     refine = [_box_mask(ext, dim, 0, (nx // 4, 0), (3 * nx // 4, ny))] if band else []
@@ -258,10 +266,10 @@ def sod(nx: int = 4096, ny: int = 8, steps: Optional[int] = None, theta: float =
         m = np.zeros((4, coords.shape[0]))
         m[0] = np.where(left, 1.0, 0.125)
         p = np.where(left, 1.0, 0.1)
-        m[3] = theta * p / m[0]
+        m[3] = theta * (p / m[0]) / (1.0 if theta_at == "left" else 0.8)
         return m
 
-    return Workload("sod", "D2Q37", "DDF_POLY", dim, ext, L, refine, [None] * L,
+    return Workload("sod", lattice, collision, dim, ext, L, refine, [None] * L,
                     faces, 0.0, steps, T0=theta, gamma=1.4, sensor_A=sensor_A,
                     sensor_on=True, init=init, storage=storage)
 

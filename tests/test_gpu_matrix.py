@@ -23,7 +23,9 @@ TOL = {"fp64": 1e-12, "fp32": 1e-4, "fp16": 3e-3}
 COMBOS = ([(lat, coll, sto) for lat in ("D2Q9", "D3Q27") for coll in ("BGK", "RR") for sto in ("fp64", "fp32", "fp16")]
           + [("D2Q37", "DDF_POLY", sto) for sto in ("fp64", "fp32")]
           + [("D2Q21", "DDF_NEWTON", sto) for sto in ("fp64", "fp32")]
-          + [("D2Q13", "DDF_NEWTON", sto) for sto in ("fp64", "fp32")])
+          + [("D2Q13", "DDF_NEWTON", sto) for sto in ("fp64", "fp32")]
+          + [(lat, coll, sto) for lat in ("D2Q13", "D2Q21") for coll in ("BGK", "RR")
+             for sto in ("fp64", "fp32", "fp16")])
 
 
 @pytest.mark.parametrize("lattice,collision,storage", COMBOS, ids=["-".join(c) for c in COMBOS])

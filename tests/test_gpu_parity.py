@@ -79,6 +79,34 @@ def test_sod_d2q37(storage, tol):
         say("[parity] sod fp32 largest |drho| at x =", np.round(xc[order], 2), "values", d[order])
 
 
+@pytest.mark.parametrize("lattice,theta", [("D2Q13", 0.35), ("D2Q21", 0.9)])
+@pytest.mark.parametrize("storage,tol", [("fp64", None), ("fp32", 5e-3)])
+def test_sod_newton(lattice, theta, storage, tol):
+    """Shock tube with the Newton numerical equilibrium on D2Q13 / D2Q21,
+    refined band, kinetic sensor, Neumann faces, to the end time.  Both
+    sides stop their Newton solves at a residual of 1e-12 (the paper's FP64
+    tolerance), so their equilibria may differ by that much in every step,
+    and the inviscid collision (omega = 2) does not damp the difference: the
+    FP64 bound is steps x 1e-12.  The FP32 bound is the sensor-switching one
+    of the D2Q37 tube."""
+    w = W.sod(nx=256, ny=8, lattice=lattice, collision="DDF_NEWTON", theta=theta, theta_at="right")
+    if storage == "fp64":
+        tol = w.steps * w.newton_tol
+    err, s, o = check(f"sod256 {lattice} newton", w, w.steps, storage, tol, tol_rho=tol)
+    st = s.stats()
+    assert st["newton_failures"] == 0 and st["newton_calls"] > 0
+
+
+@pytest.mark.parametrize("lattice", ["D2Q13", "D2Q21"])
+@pytest.mark.parametrize("storage,tol", [("fp64", FP64_TOL), ("fp32", 1e-4)])
+def test_cavity_third_order_rr(lattice, storage, tol):
+    """Two-level lid-driven cavity with RR on the third-order lattices:
+    walls and the moving lid under populations that cross two or three
+    cells, interfaces with two or three ghost layers"""
+    w = W.cavity(n=64, steps=300, lattice=lattice, collision="RR", storage=storage)
+    check(f"cavity64 {lattice} RR", w, 300, storage, tol)
+
+
 @pytest.mark.parametrize("storage,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
 def test_airfoil_d2q21_newton(storage, tol):
     """D2Q21 numerical equilibrium (Newton), three levels, equilibrium

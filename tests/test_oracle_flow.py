@@ -59,7 +59,8 @@ def test_one_level_tree_equals_cartesian_update():
 
 
 CONS_CASES = [("D2Q9", "BGK", 3, 32), ("D2Q9", "RR", 3, 32), ("D3Q27", "RR", 2, 8),
-              ("D2Q37", "DDF_POLY", 2, 32), ("D2Q21", "DDF_NEWTON", 2, 32)]
+              ("D2Q37", "DDF_POLY", 2, 32), ("D2Q21", "DDF_NEWTON", 2, 32),
+              ("D2Q13", "RR", 3, 32), ("D2Q21", "RR", 2, 32), ("D2Q13", "DDF_NEWTON", 2, 32)]
 
 
 @pytest.mark.parametrize("lat,coll,levels,n", CONS_CASES)
@@ -68,7 +69,7 @@ def test_refined_periodic_conservation(lat, coll, levels, n):
     coalesced) are invariant on a periodic refined domain: coalescence and
     uniform explosion are conservative (Sec. 3.2)."""
     w = W.shear(n=n, levels=levels, lattice=lat, collision=coll, kind="random", u0=0.03,
-                nu_finest=0.02, band=[(0.25, 0.75), (0.375, 0.625)])
+                nu_finest=0.02, band=[(0.25, 0.75), (0.375, 0.625)], T0=0.35 if lat == "D2Q13" else 1.0)
     if lat == "D2Q37":
         w.T0 = 0.65
     if lat == "D2Q21":
@@ -243,8 +244,8 @@ def test_poiseuille_profile_second_order(coll, levels):
     assert dev[8] / dev[16] > 3.2, dev
 
 
-def sod_error(nx):
-    w = W.sod(nx=nx, ny=4, band=True)
+def sod_error(nx, **kw):
+    w = W.sod(nx=nx, ny=4, band=True, **kw)
     o = Oracle.from_workload(w)
     o.init_workload(w)
     o.step(w.steps)
@@ -253,7 +254,10 @@ def sod_error(nx):
     ok = ~np.isnan(m[0])
     lev = e["level"][ok]
     xc = (e["coords"][ok, 0] + 0.5) / 2.0 ** lev
-    t = w.steps * math.sqrt(w.T0)  # lattice time in units where c = sqrt(gamma p / rho)
+    # lattice time in units of the exact solution (left state p = rho = 1):
+    # velocities scale with the square root of the left temperature
+    t_left = w.T0 / (0.8 if kw.get("theta_at") == "right" else 1.0)
+    t = w.steps * math.sqrt(t_left)
     ex = riemann_exact.sample((xc - nx / 2) / t, 1.0, 0.0, 1.0, 0.125, 0.0, 0.1, 1.4)
     vol = 0.25 ** lev
     return np.sum(vol * np.abs(m[0][ok] - ex[0])) / np.sum(vol), m
@@ -266,4 +270,20 @@ def test_sod_against_exact_riemann():
     e512, _ = sod_error(512)
     assert e256 < 6e-3
     assert e512 < 0.75 * e256
+    assert np.nanmin(m[0]) > 0.12 and np.nanmax(m[0]) < 1.001
+
+
+@pytest.mark.parametrize("lattice,theta", [("D2Q13", 0.35), ("D2Q21", 0.9)])
+def test_sod_numerical_equilibrium_against_exact_riemann(lattice, theta):
+    """The same inviscid shock tube with the double-distribution Newton
+    equilibrium on D2Q13 and D2Q21 at the paper's inviscid reference
+    temperatures (Sec. 6), the right (reference) state at T0: the density
+    converges to the exact Riemann solution.  With the left state at T0 the
+    D2Q13 star state (u about 0.55, T about 0.25) lies outside what its
+    eight-moment exponential can represent and the Newton solve fails."""
+    kw = dict(lattice=lattice, collision="DDF_NEWTON", theta=theta, theta_at="right")
+    e256, m = sod_error(256, **kw)
+    e512, _ = sod_error(512, **kw)
+    assert e256 < 4e-3, e256
+    assert e512 < 0.75 * e256, (e256, e512)
     assert np.nanmin(m[0]) > 0.12 and np.nanmax(m[0]) < 1.001
