@@ -1348,6 +1348,34 @@ int ol_get_state(const ol_sim *s, double *f, double *g, double *lam) {
   return 0;
 }
 
+int ol_get_sync_state(ol_sim *s, double *f, double *g, double *lam) {
+  if (!s->have_state) return fail(s, -5, "not initialised");
+  if (!f || (is_ddf(s) && !g)) return fail(s, -1, "null output");
+  sync_state(s, f, is_ddf(s) ? g : NULL);
+  if (lam) memcpy(lam, s->lam, s->n * NLAM * sizeof(double));
+  return 0;
+}
+
+int ol_set_state(ol_sim *s, const double *f, const double *g, const double *lam) {
+  if (!s->have_grid) return fail(s, -5, "no grid");
+  if (!f || (is_ddf(s) && !g)) return fail(s, -1, "null populations");
+  int64_t n = s->n;
+  int Q = s->Q, ddf = is_ddf(s);
+  free(s->f); free(s->fs); free(s->g); free(s->gs); free(s->lam); free(s->collided);
+  s->f = (double *)malloc(n * Q * sizeof(double));
+  s->fs = (double *)calloc(n * Q, sizeof(double));
+  s->g = ddf ? (double *)malloc(n * Q * sizeof(double)) : NULL;
+  s->gs = ddf ? (double *)calloc(n * Q, sizeof(double)) : NULL;
+  s->lam = (double *)calloc(n * NLAM, sizeof(double));
+  s->collided = (uint8_t *)calloc(n, 1);
+  memcpy(s->f, f, n * Q * sizeof(double));
+  if (ddf) memcpy(s->g, g, n * Q * sizeof(double));
+  if (lam) memcpy(s->lam, lam, n * NLAM * sizeof(double));
+  s->numeric_error = 0;
+  s->have_state = 1;
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Single-cell entry points used by the tests                                */
 /* ------------------------------------------------------------------------ */

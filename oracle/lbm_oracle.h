@@ -73,6 +73,12 @@ int ol_set_face(ol_sim *s, int face, const ol_face *f);
 int ol_counters(const ol_sim *s, int64_t *updates_per_level,
                 int64_t *newton_iters, int64_t *newton_calls);
 int ol_get_state(const ol_sim *s, double *f, double *g, double *lam);
+/* the synchronisation-point state: as ol_get_state, with the unknown
+ * populations of every coarse ghost coalesced from its children */
+int ol_get_sync_state(ol_sim *s, double *f, double *g, double *lam);
+/* replaces the state of every cell by the given pre-collision populations
+ * (and multipliers); [n][Q] / [n][8] like ol_get_state */
+int ol_set_state(ol_sim *s, const double *f, const double *g, const double *lam);
 
 /* single-cell routines (tau given, no sponge) */
 int ol_feq(ol_sim *s, double rho, const double *u, double T, double *feq,

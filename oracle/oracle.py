@@ -74,6 +74,8 @@ def lib():
         L.ol_set_face.argtypes = [vp, C.c_int, C.POINTER(Face)]
         L.ol_counters.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_void_p]
         L.ol_get_state.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.ol_set_state.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.ol_get_sync_state.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_void_p]
         L.ol_feq.argtypes = [vp, C.c_double, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
         L.ol_collide.argtypes = [vp, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p]
@@ -175,6 +177,7 @@ class Oracle:
             sp = (C.c_void_p * len(sol))(*[_ptr(a) for a in sol])
         fa = (Face * 6)(*[make_face(f) for f in faces])
         self._check(self._L.ol_grid(self.h, dim, _ptr(e), n_levels, rp, sp, fa))
+        self._ext, self._faces = tuple(ext), list(faces)
         self.n = self._L.ol_n_cells(self.h)
         self.n_levels = n_levels
         self.dim = dim
@@ -233,6 +236,21 @@ class Oracle:
         lam = np.zeros((self.n, 8))
         self._check(self._L.ol_get_state(self.h, _ptr(f), _ptr(g), _ptr(lam)))
         return f, g, lam
+
+    def sync_state(self):
+        """state with every coarse ghost's unknown populations coalesced"""
+        f = np.zeros((self.n, self.Q))
+        g = np.zeros((self.n, self.Q)) if self.ddf else None
+        lam = np.zeros((self.n, 8))
+        self._check(self._L.ol_get_sync_state(self.h, _ptr(f), _ptr(g), _ptr(lam)))
+        return f, g, lam
+
+    def set_state(self, f, g=None, lam=None):
+        """pre-collision populations [n][Q] (g likewise, multipliers [n][8])"""
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        g = None if g is None else np.ascontiguousarray(g, dtype=np.float64)
+        lam = None if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
+        self._check(self._L.ol_set_state(self.h, _ptr(f), _ptr(g), _ptr(lam)))
 
     def tau(self, level):
         return self._L.ol_tau(self.h, level)

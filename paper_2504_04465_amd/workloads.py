@@ -329,6 +329,51 @@ def airfoil(scale: int = 1, steps: int = 1000, Ma: float = 1.5, Ma0: float = 1.0
 
 
 # --------------------------------------------------------------------------
+# convected vortex with refinement patches that follow it (the adaptive runs
+# of Sec. 8): periodic box, vortex carried along x
+# --------------------------------------------------------------------------
+def vortex(n: int = 64, levels: int = 3, lattice: str = "D2Q9", collision: str = "RR",
+           u0: float = 0.05, eps: float = 0.02, radius: Optional[float] = None, nu_finest: float = 1e-3,
+           steps: int = 64, storage: str = "fp64", T0: float = 1.0) -> Workload:
+    """Gaussian vortex of radius R = n/16 (strength eps) at (n/4, n/2) in a
+    uniform flow u0 along x.  `patch(t)` returns the refinement masks of
+    nested square patches centred on where the vortex is after t coarse
+    steps (half-widths 3R at level 0, 3R - 4 coarse cells deeper); the
+    workload starts with patch(0)."""
+    dim, ext = 2, (n, n)
+    R = radius if radius is not None else n / 16.0
+    x0, y0 = n / 4.0, n / 2.0
+    ddf = collision.startswith("DDF")
+
+    def patch(t):
+        xc = x0 + u0 * t
+        masks = []
+        for l in range(levels - 1):
+            h = 3.0 * R - 4.0 * l
+            lo = (max(0, int(math.floor(xc - h))), max(0, int(math.floor(y0 - h))))
+            hi = (min(n, int(math.ceil(xc + h))), min(n, int(math.ceil(y0 + h))))
+            masks.append(_box_mask(ext, dim, l, lo, hi))
+        return masks
+
+    def init(coords, level):
+        xc = _centre_coords(coords, level)
+        dx, dy = (xc[:, 0] - x0) / R, (xc[:, 1] - y0) / R
+        e = np.exp(-0.5 * (dx * dx + dy * dy))
+        m = np.zeros((1 + dim + (1 if ddf else 0), coords.shape[0]))
+        m[0] = 1.0 - 0.5 * eps * eps * e * e
+        m[1] = u0 - eps * dy * e
+        m[2] = eps * dx * e
+        if ddf:
+            m[3] = T0
+        return m
+
+    w = Workload("vortex", lattice, collision, dim, ext, levels, patch(0), [None] * levels,
+                 [Face() for _ in range(6)], nu_finest, steps, T0=T0, init=init, storage=storage)
+    w.patch = patch
+    return w
+
+
+# --------------------------------------------------------------------------
 # periodic shear layers across refinement interfaces (tests)
 # --------------------------------------------------------------------------
 def shear(n: int = 32, levels: int = 2, lattice: str = "D2Q9", collision: str = "BGK",

@@ -1,0 +1,114 @@
+"""Pins of the oracle's mesh adaptation (Sec. 8: populations copied where
+the old tree has the cell, uniformly exploded where the new tree is finer,
+coalesced where it is coarser).  Closed forms and invariants: the
+volume-weighted sums of mass, momentum and energy over the cells that tile
+the domain are unchanged by a remesh; remeshing to the same masks changes
+nothing; refining and coarsening back restores the state; a coarsened cell
+holds the volume mean of the old cells inside it, found here by an
+independent vectorised search; a refined cell holds its old parent's
+populations."""
+import numpy as np
+import pytest
+
+from oracle.oracle import F_FINE_GHOST, Oracle
+from oracle.remesh import remesh
+from paper_2504_04465_amd import workloads as W
+
+
+def vortex_oracle(lattice="D2Q9", collision="RR", levels=3, T0=1.0):
+    w = W.vortex(n=64, levels=levels, lattice=lattice, collision=collision, T0=T0)
+    o = Oracle.from_workload(w)
+    o.init_workload(w)
+    return w, o
+
+
+CASES = [("D2Q9", "RR", 1.0), ("D2Q13", "RR", 1.0), ("D2Q21", "DDF_NEWTON", 0.65)]
+
+
+@pytest.mark.parametrize("lattice,collision,T0", CASES)
+def test_remesh_conserves_sums(lattice, collision, T0):
+    w, o = vortex_oracle(lattice, collision, T0=T0)
+    o.step(4)
+    for t in (20, 40):  # the patches move by one and two coarse cells
+        s0 = o.sums()
+        c0 = o.export()["coords"]
+        remesh(o, w.patch(t))
+        s1 = o.sums()
+        c1 = o.export()["coords"]
+        assert c1.shape != c0.shape or not np.array_equal(c1, c0)
+        # the two sums run over different cell sets of ~1e4 terms: rounding
+        # of order sqrt(n) eps relative; a lost or doubled cell is 1e-4
+        assert np.max(np.abs(s1 - s0)) < 5e-14 * np.max(np.abs(s0)), (s0, s1)
+
+
+def test_remesh_same_masks_is_identity():
+    w, o = vortex_oracle()
+    o.step(4)
+    f0, _, _ = o.sync_state()
+    e0 = o.export()
+    remesh(o, w.patch(0))
+    f1, _, _ = o.sync_state()
+    assert np.array_equal(o.export()["coords"], e0["coords"])
+    keep = (e0["flags"] & F_FINE_GHOST) == 0
+    assert np.array_equal(f1[keep], f0[keep])
+
+
+def grown(w, by):
+    """the workload's level boxes, each widened by `by` coarse cells"""
+    out = []
+    for l, m in enumerate(w.refine):
+        s = 1 << l
+        lo = [m.lo[a] // s - by for a in range(2)]
+        hi = [(m.lo[a] + m.n[a]) // s + by for a in range(2)]
+        out.append(W._box_mask(w.ext, 2, l, tuple(lo), tuple(hi)))
+    return out
+
+
+def test_refine_then_coarsen_restores_state():
+    """refining everywhere the grid is refined already (a superset) and
+    coarsening back: explosion then coalescence of 2^D equal copies"""
+    w, o = vortex_oracle()
+    o.step(4)
+    f0, _, _ = o.sync_state()
+    e0 = o.export()
+    remesh(o, grown(w, 2))
+    assert o.n > len(e0["level"])
+    remesh(o, w.patch(0))
+    f1, _, _ = o.sync_state()
+    e1 = o.export()
+    assert np.array_equal(e1["coords"], e0["coords"]) and np.array_equal(e1["level"], e0["level"])
+    keep = (e0["flags"] & F_FINE_GHOST) == 0
+    assert np.max(np.abs(f1[keep] - f0[keep])) < 4e-16 * np.max(np.abs(f0))
+
+
+def test_coarsened_cell_is_volume_mean_and_refined_cell_copies_parent():
+    w, o = vortex_oracle(levels=2)
+    o.step(4)
+    f0, _, _ = o.sync_state()
+    e0 = o.export()
+    remesh(o, w.patch(40))
+    f1, _, _ = o.sync_state()
+    e1 = o.export()
+    tile0 = (e0["flags"] & F_FINE_GHOST) == 0
+    # level-0 cells of the new grid whose place was refined before: mean of
+    # the old level-1 cells inside (vectorised search over coordinates)
+    c0 = e0["coords"][:, :2]
+    checked_mean = checked_copy = 0
+    for j in np.where((e1["level"] == 0) & ((e1["flags"] & F_FINE_GHOST) == 0))[0]:
+        x, y = e1["coords"][j, :2]
+        same = tile0 & (e0["level"] == 0) & (c0[:, 0] == x) & (c0[:, 1] == y)
+        if same.any():
+            continue
+        kids = tile0 & (e0["level"] == 1) & (c0[:, 0] // 2 == x) & (c0[:, 1] // 2 == y)
+        assert kids.sum() == 4
+        assert np.max(np.abs(f1[j] - f0[kids].mean(axis=0))) < 1e-15
+        checked_mean += 1
+    # level-1 cells of the new grid over an old level-0 cell: its copy
+    for j in np.where(e1["level"] == 1)[0]:
+        x, y = e1["coords"][j, :2]
+        par = tile0 & (e0["level"] == 0) & (c0[:, 0] == x // 2) & (c0[:, 1] == y // 2)
+        if not par.any():
+            continue
+        assert np.array_equal(f1[j], f0[np.where(par)[0][0]])
+        checked_copy += 1
+    assert checked_mean > 10 and checked_copy > 10
