@@ -239,6 +239,25 @@ lbm_status lbm_profile_read(lbm_ctx *ctx, int level, int64_t *launches,
  * g [Q][n_cells] (DDF only, else may be NULL), lambda [8][n_cells] (D2Q21
  * only, else may be NULL).  lbm_set_state restores such a state. */
 lbm_status lbm_get_state(lbm_ctx *ctx, double *f, double *g, double *lambda);
+
+/* Mesh adaptation (Sec. 8, methodology of the adaptive runs): replaces the
+ * grid by the one the new refinement masks (and solid masks, as in
+ * lbm_grid_build; extent, level count and faces unchanged) describe, and
+ * moves the state across at the synchronisation point.  Every new cell,
+ * ghosts included, takes the pre-collision populations (and multipliers)
+ * of the old grid's cells other than fine ghosts (coarse ghosts with their
+ * unknown populations coalesced; these cells tile the domain): copied
+ * from the old cell at the same place and level, or from the old cell that
+ * contains it where the old grid is coarser (uniform explosion), or
+ * averaged over the old cells inside it, weighted by volume, where the old
+ * grid is finer (coalescence).  The move runs on the device; the new tree
+ * is built on the host.  Cell numbering, layout and all device buffers are
+ * replaced (re-read lbm_grid_info / lbm_grid_export); step and update
+ * counts carry over, Newton / surrogate counters restart, surrogate
+ * weights are kept.  Errors: LBM_E_STATE without a state, LBM_E_MASK for
+ * inconsistent masks or a new fluid cell over old solid cells (the context
+ * then has a grid and no state), LBM_E_NOMEM. */
+lbm_status lbm_remesh(lbm_ctx *ctx, const lbm_mask *refine, const lbm_mask *solid);
 lbm_status lbm_set_state(lbm_ctx *ctx, const double *f, const double *g,
                          const double *lambda);
 

@@ -19,6 +19,8 @@
 
 #include <random>
 
+#include "remesh.h"
+
 using namespace lbm;
 
 struct ProfSlot {
@@ -680,25 +682,33 @@ lbm_status lbm_grid_export(lbm_ctx *c, int32_t *coords, int8_t *level, uint8_t *
   return LBM_OK;
 }
 
+// mode 0: moments, 1: populations (and multipliers); the sources are host
+// arrays, or device arrays when on_device (then used in place)
 static lbm_status init_common(lbm_ctx *c, const double *src, const double *src_g, const double *src_lam,
-                              int mode) {
+                              int mode, bool on_device = false) {
   if (!c) return LBM_E_ARG;
   if (c->p.host_only) return set_err(c, LBM_E_STATE, "context is host-only");
   if (!c->have_grid) return set_err(c, LBM_E_STATE, "no grid");
   const int64_t n = c->N;
   const size_t rows = mode == 0 ? (size_t)n_mom(c) : (size_t)c->lat.Q;
-  const size_t need = rows * n + (mode == 1 && c->ddf ? rows * n : 0) + (mode == 1 && src_lam ? NLAM * n : 0);
-  double *d = scratch(c, sizeof(double) * std::max<size_t>(need, 1));
-  if (!d) return set_err(c, LBM_E_NOMEM, "scratch allocation failed");
-  HIP_TRY(c, hipMemcpyAsync(d, src, sizeof(double) * rows * n, hipMemcpyHostToDevice, c->stream));
-  double *dg = nullptr, *dl = nullptr;
-  if (mode == 1 && c->ddf) {
-    dg = d + rows * n;
-    HIP_TRY(c, hipMemcpyAsync(dg, src_g, sizeof(double) * rows * n, hipMemcpyHostToDevice, c->stream));
-  }
-  if (mode == 1 && src_lam && c->lamf) {
-    dl = d + rows * n * (c->ddf ? 2 : 1);
-    HIP_TRY(c, hipMemcpyAsync(dl, src_lam, sizeof(double) * NLAM * n, hipMemcpyHostToDevice, c->stream));
+  double *d = nullptr, *dg = nullptr, *dl = nullptr;
+  if (on_device) {
+    d = (double *)src;
+    dg = mode == 1 && c->ddf ? (double *)src_g : nullptr;
+    dl = mode == 1 && c->lamf ? (double *)src_lam : nullptr;
+  } else {
+    const size_t need = rows * n + (mode == 1 && c->ddf ? rows * n : 0) + (mode == 1 && src_lam ? NLAM * n : 0);
+    d = scratch(c, sizeof(double) * std::max<size_t>(need, 1));
+    if (!d) return set_err(c, LBM_E_NOMEM, "scratch allocation failed");
+    HIP_TRY(c, hipMemcpyAsync(d, src, sizeof(double) * rows * n, hipMemcpyHostToDevice, c->stream));
+    if (mode == 1 && c->ddf) {
+      dg = d + rows * n;
+      HIP_TRY(c, hipMemcpyAsync(dg, src_g, sizeof(double) * rows * n, hipMemcpyHostToDevice, c->stream));
+    }
+    if (mode == 1 && src_lam && c->lamf) {
+      dl = d + rows * n * (c->ddf ? 2 : 1);
+      HIP_TRY(c, hipMemcpyAsync(dl, src_lam, sizeof(double) * NLAM * n, hipMemcpyHostToDevice, c->stream));
+    }
   }
   HIP_TRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long) * CNT_COUNT * CNT_COPIES, c->stream));
   IArgs a{};
@@ -738,6 +748,103 @@ lbm_status lbm_set_state(lbm_ctx *c, const double *f, const double *g, const dou
   if (!f) return set_err(c, LBM_E_ARG, "null populations");
   if (c && c->ddf && !g) return set_err(c, LBM_E_ARG, "DDF state needs g");
   return init_common(c, f, g, lambda, 1);
+}
+
+lbm_status lbm_remesh(lbm_ctx *c, const lbm_mask *refine, const lbm_mask *solid) {
+  lbm_status s = need_state(c);
+  if (s != LBM_OK) return s;
+  if (c->L > 1 && !refine) return set_err(c, LBM_E_ARG, "refine masks missing");
+  // 1. the old tree's synchronisation-point state, canonical [rows][n_old],
+  //    in a buffer of its own (the new grid releases the context's memory)
+  const int Q = c->lat.Q;
+  const int pop_rows = Q * (c->ddf ? 2 : 1);
+  const int rows = pop_rows + (c->lamf ? NLAM : 0);
+  const int64_t n_old = c->N;
+  double *old = nullptr;
+  {
+    const size_t bytes = sizeof(double) * (size_t)rows * (size_t)std::max<int64_t>(n_old, 1);
+    if (c->dalloc) old = (double *)c->dalloc(bytes, c->actx);
+    else if (hipMalloc((void **)&old, bytes) != hipSuccess) old = nullptr;
+    if (!old) return set_err(c, LBM_E_NOMEM, "remesh: state buffer allocation failed");
+  }
+  auto release_old = [&]() {
+    hipStreamSynchronize(c->stream);
+    if (c->dfree) c->dfree(old, c->actx);
+    else hipFree(old);
+  };
+  coalesce_all(c);
+  for (int l = 0; l < c->L; ++l) {
+    MArgs a = gather_args(c, l, 1);
+    a.out = old;
+    a.lam_out = c->lamf ? old + (size_t)pop_rows * n_old : nullptr;
+    c->ops.gather(a, c->pre[l], c->stream);
+  }
+  if ((s = check_launch(c)) != LBM_OK) {
+    release_old();
+    return s;
+  }
+  // 2. the new tree: same extent, levels and faces
+  HostGrid prev = std::move(c->g);
+  std::vector<float> mlpw;
+  if (c->have_mlp) {
+    mlpw.resize(MLP_PARAMS);
+    HIP_TRY(c, hipMemcpy(mlpw.data(), c->d_mlp_w, sizeof(float) * MLP_PARAMS, hipMemcpyDeviceToHost));
+  }
+  lbm_face_bc faces[6];
+  for (int k = 0; k < 6; ++k) faces[k] = c->face[k];
+  const int64_t steps = c->coarse_steps;
+  int64_t upd[8];
+  memcpy(upd, c->updates, sizeof upd);
+  s = lbm_grid_build(c, prev.D, prev.ext, prev.L, refine, solid, faces);
+  if (s != LBM_OK) {
+    release_old();
+    return s;
+  }
+  // 3. where every new cell takes its state from
+  std::vector<int64_t> off;
+  std::vector<int32_t> src;
+  std::vector<double> wt;
+  std::string err;
+  if (remesh_sources(prev, c->g, &off, &src, &wt, &err) != 0) {
+    release_old();
+    c->have_state = false;
+    return set_err(c, LBM_E_MASK, err);
+  }
+  // 4. move it across on the device and start the new tree from it
+  int64_t *d_off = nullptr;
+  int32_t *d_src = nullptr;
+  double *d_wt = nullptr;
+  if ((s = upload(c, &d_off, off.data(), off.size())) != LBM_OK ||
+      (s = upload(c, &d_src, src.data(), src.size())) != LBM_OK ||
+      (s = upload(c, &d_wt, wt.data(), wt.size())) != LBM_OK) {
+    release_old();
+    return s;
+  }
+  const int64_t n_new = c->N;
+  double *nw = scratch(c, sizeof(double) * (size_t)rows * (size_t)std::max<int64_t>(n_new, 1));
+  if (!nw) {
+    release_old();
+    return set_err(c, LBM_E_NOMEM, "scratch allocation failed");
+  }
+  launch_remap(old, n_old, nw, n_new, rows, d_off, d_src, d_wt, c->stream);
+  if ((s = check_launch(c)) != LBM_OK) {
+    release_old();
+    return s;
+  }
+  s = init_common(c, nw, c->ddf ? nw + (size_t)Q * n_new : nullptr,
+                  c->lamf ? nw + (size_t)pop_rows * n_new : nullptr, 1, true);
+  release_old();
+  dev_release(c, d_off);
+  dev_release(c, d_src);
+  dev_release(c, d_wt);
+  if (s != LBM_OK) return s;
+  c->coarse_steps = steps;
+  memcpy(c->updates, upd, sizeof upd);
+  if (!mlpw.empty()) {
+    if ((s = mlp_ensure(c)) != LBM_OK) return s;
+    return mlp_upload_weights(c, mlpw.data());
+  }
+  return LBM_OK;
 }
 
 }  // extern "C"

@@ -28,6 +28,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_MASK", -3: "LBM_E_NOMEM", -4:
 EXPORTS = ["lbm_create", "lbm_grid_build", "lbm_grid_info", "lbm_layout_info", "lbm_grid_export", "lbm_init",
            "lbm_step", "lbm_set_face_bc", "lbm_set_graphs", "lbm_moments", "lbm_moments_device", "lbm_stats_get",
            "lbm_sync", "lbm_profile_enable", "lbm_profile_read", "lbm_get_state", "lbm_get_cells", "lbm_set_state",
+           "lbm_remesh",
            "lbm_last_error", "lbm_destroy", "lbm_mlp_set_weights", "lbm_mlp_get_weights",
            "lbm_mlp_label", "lbm_mlp_predict", "lbm_mlp_grad", "lbm_mlp_train"]
 MLP_PARAMS = 9176
@@ -98,6 +99,7 @@ def lib():
         L.lbm_profile_read.argtypes = [vp, C.c_int, vp, vp, vp]
         L.lbm_get_state.argtypes = [vp, vp, vp, vp]
         L.lbm_set_state.argtypes = [vp, vp, vp, vp]
+        L.lbm_remesh.argtypes = [vp, vp, vp]
         L.lbm_get_cells.argtypes = [vp, vp, i64, vp, vp, vp]
         L.lbm_last_error.restype = C.c_char_p
         L.lbm_last_error.argtypes = [vp]
@@ -230,6 +232,23 @@ class LBM:
         data shaped (ny, nx) or (nz, ny, nx)) or None."""
         self.dim, self.n_levels = dim, n_levels
         e = np.array(list(ext) + [1] * (3 - len(ext)), np.int32)
+        ra, sa, keep = self._masks(refine, solid, n_levels)
+        fa = (FaceBC * 6)(*[face_struct(f) for f in faces])
+        self._check(self._L.lbm_grid_build(self.h, dim, _ptr(e), n_levels, C.cast(ra, C.c_void_p),
+                                           None if sa is None else C.cast(sa, C.c_void_p),
+                                           C.cast(fa, C.c_void_p)), "lbm_grid_build")
+        self._grid_info()
+
+    def remesh(self, refine, solid=None):
+        """adapt the grid to new refinement (and solid) masks, moving the
+        state across (lbm_remesh); extent, levels and faces are kept"""
+        ra, sa, keep = self._masks(refine, solid, self.n_levels)
+        self._check(self._L.lbm_remesh(self.h, C.cast(ra, C.c_void_p),
+                                       None if sa is None else C.cast(sa, C.c_void_p)), "lbm_remesh")
+        self._grid_info()
+
+    @staticmethod
+    def _masks(refine, solid, n_levels):
         keep = []
 
         def mk(m):
@@ -249,10 +268,10 @@ class LBM:
         sa = None
         if solid is not None and any(s is not None for s in solid):
             sa = (MaskC * n_levels)(*[mk(solid[l] if l < len(solid) else None) for l in range(n_levels)])
-        fa = (FaceBC * 6)(*[face_struct(f) for f in faces])
-        self._check(self._L.lbm_grid_build(self.h, dim, _ptr(e), n_levels, C.cast(ra, C.c_void_p),
-                                           None if sa is None else C.cast(sa, C.c_void_p),
-                                           C.cast(fa, C.c_void_p)), "lbm_grid_build")
+        return ra, sa, keep
+
+    def _grid_info(self):
+        n_levels, dim = self.n_levels, self.dim
         n = C.c_int64()
         npl = np.zeros(8, np.int64)
         ng = C.c_int64()
