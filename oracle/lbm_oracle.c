@@ -1102,6 +1102,17 @@ int ol_init(ol_sim *s, const double *mom) {
 /* Time stepping                                                             */
 /* ------------------------------------------------------------------------ */
 
+/* population i of coarse ghost G is coalesced from the children unless the
+ * coarse level itself supplies it: its pull source at G's level is a cell
+ * outside the refined region (a boundary sentinel counts as supplied); a
+ * source that is missing or is another coarse ghost lies in the overlap,
+ * where the fine level carries the flow */
+static int coalesced_pop(const ol_sim *s, int64_t G, int i) {
+  int32_t v = s->nbr[G * (s->Q - 1) + i - 1];
+  if (v == OL_NONE) return 1;
+  return v >= 0 && (s->flag[v] & OL_F_COARSE_GHOST);
+}
+
 /* Rohde coupling between level l (coarse) and l+1 (fine): coalescence of the
  * unknown coarse-ghost populations, collision of the coarse ghost, uniform
  * explosion of its post-collision state into all of its children. */
@@ -1115,7 +1126,7 @@ static void coupling(ol_sim *s, int l) {
     int nf = 0;
     for (int o = 0; o < nch; ++o) nf += ch[o] >= 0;
     for (int i = 1; i < Q; ++i) {
-      if (s->nbr[G * Qm + i - 1] != OL_NONE) continue;
+      if (!coalesced_pop(s, G, i)) continue;
       double af = 0.0, ag = 0.0;
       for (int o = 0; o < nch; ++o) {
         if (ch[o] < 0) continue;
@@ -1266,7 +1277,7 @@ static void sync_state(const ol_sim *s, double *f, double *g) {
     int nf = 0;
     for (int o = 0; o < nch; ++o) nf += ch[o] >= 0;
     for (int i = 1; i < Q; ++i) {
-      if (s->nbr[G * Qm + i - 1] != OL_NONE) continue;
+      if (!coalesced_pop(s, G, i)) continue;
       double af = 0.0, ag = 0.0;
       for (int o = 0; o < nch; ++o) {
         if (ch[o] < 0) continue;
