@@ -437,9 +437,15 @@ int build_grid(const LatticeInfo &lat, int dim, const int32_t ext_in[3], int L,
       const int32_t Z = D == 3 ? 2 * g.xyz[3 * c + 2] + ((o >> 2) & 1) : 0;
       if (f.inside(X, Y, Z)) g.child[(size_t)k * NCH + o] = f.idx[f.lin(X, Y, Z)];
     }
+    // coalesced: populations the coarse level does not supply itself, i.e.
+    // whose pull source at this level is missing or is another coarse ghost
+    // (in the overlap the fine level carries the flow; taking such a
+    // population from the neighbouring ghost double-counts at corners)
     uint64_t m = 0;
-    for (int i = 1; i < Q; ++i)
-      if (g.nbr[(size_t)(i - 1) * n + c] == NBR_NONE) m |= (uint64_t)1 << i;
+    for (int i = 1; i < Q; ++i) {
+      const int32_t v = g.nbr[(size_t)(i - 1) * n + c];
+      if (v == NBR_NONE || (v >= 0 && (g.flag[v] & F_COARSE_GHOST))) m |= (uint64_t)1 << i;
+    }
     g.unknown[k] = m;
   }
   return 0;

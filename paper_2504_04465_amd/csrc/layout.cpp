@@ -192,7 +192,9 @@ int build_layout(const HostGrid &g, const LatticeInfo &lat, const bool periodic[
     for (int i = 0; i < Qm; ++i) {
       const int32_t v = g.nbr[(size_t)i * n + c];
       int32_t o;
-      if (v >= 0) o = y.slot_of[v];
+      // a coarse ghost reads its coalesced slot for every population the
+      // coarse level does not supply: no source, or another coarse ghost
+      if (v >= 0) o = (gidx[c] >= 0 && gidx[v] >= 0) ? (int32_t)(vbase + gidx[c]) : y.slot_of[v];
       else if (v == NBR_NONE) o = gidx[c] >= 0 ? (int32_t)(vbase + gidx[c]) : (int32_t)s;
       else if (v == NBR_SOLID) o = -1;
       else o = -2 - (-3 - v);
