@@ -1367,6 +1367,32 @@ int ol_get_sync_state(ol_sim *s, double *f, double *g, double *lam) {
   return 0;
 }
 
+int ol_sensor(ol_sim *s, double *eps) {
+  if (!s->have_state) return fail(s, -5, "not initialised");
+  int Q = s->Q, ddf = is_ddf(s);
+  int64_t n = s->n;
+  double *f = (double *)malloc(n * Q * sizeof(double));
+  double *g = ddf ? (double *)malloc(n * Q * sizeof(double)) : NULL;
+  sync_state(s, f, g);
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+  for (int64_t c = 0; c < n; ++c) {
+    if (s->flag[c] & OL_F_FINE_GHOST) {
+      eps[c] = NAN;
+      continue;
+    }
+    moments_t mo = cell_moments(s, f + c * Q, ddf ? g + c * Q : NULL);
+    double feq[MAXQ], geq[MAXQ], lam[NLAM];
+    memcpy(lam, s->lam + c * NLAM, sizeof lam);
+    if (equilibrium(s, mo.rho, mo.u, mo.T, feq, ddf ? geq : NULL, lam) != 0) bad = 1;
+    sensor_alpha(s, f + c * Q, feq, 1.0, &eps[c]);
+  }
+  free(f);
+  free(g);
+  if (bad) return fail(s, -6, "Newton did not converge in the sensor");
+  return 0;
+}
+
 int ol_set_state(ol_sim *s, const double *f, const double *g, const double *lam) {
   if (!s->have_grid) return fail(s, -5, "no grid");
   if (!f || (is_ddf(s) && !g)) return fail(s, -1, "null populations");

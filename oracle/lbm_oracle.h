@@ -76,6 +76,9 @@ int ol_get_state(const ol_sim *s, double *f, double *g, double *lam);
 /* the synchronisation-point state: as ol_get_state, with the unknown
  * populations of every coarse ghost coalesced from its children */
 int ol_get_sync_state(ol_sim *s, double *f, double *g, double *lam);
+/* kinetic sensor (Eq. DeltaAvg) of every cell at the synchronisation
+ * point against the equilibrium at its own moments; NaN for fine ghosts */
+int ol_sensor(ol_sim *s, double *eps);
 /* replaces the state of every cell by the given pre-collision populations
  * (and multipliers); [n][Q] / [n][8] like ol_get_state */
 int ol_set_state(ol_sim *s, const double *f, const double *g, const double *lam);

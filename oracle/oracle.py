@@ -76,6 +76,7 @@ def lib():
         L.ol_get_state.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_void_p]
         L.ol_set_state.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_void_p]
         L.ol_get_sync_state.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.ol_sensor.argtypes = [vp, C.c_void_p]
         L.ol_feq.argtypes = [vp, C.c_double, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
         L.ol_collide.argtypes = [vp, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p]
@@ -244,6 +245,12 @@ class Oracle:
         lam = np.zeros((self.n, 8))
         self._check(self._L.ol_get_sync_state(self.h, _ptr(f), _ptr(g), _ptr(lam)))
         return f, g, lam
+
+    def sensor(self):
+        """kinetic sensor eps per cell (Eq. DeltaAvg), NaN for fine ghosts"""
+        out = np.zeros(self.n)
+        self._check(self._L.ol_sensor(self.h, _ptr(out)))
+        return out
 
     def set_state(self, f, g=None, lam=None):
         """pre-collision populations [n][Q] (g likewise, multipliers [n][8])"""

@@ -10,7 +10,7 @@ populations."""
 import numpy as np
 import pytest
 
-from oracle.oracle import F_FINE_GHOST, Oracle
+from oracle.oracle import F_COARSE_GHOST, F_FINE_GHOST, Oracle
 from oracle.remesh import remesh
 from paper_2504_04465_amd import workloads as W
 
@@ -112,3 +112,46 @@ def test_coarsened_cell_is_volume_mean_and_refined_cell_copies_parent():
         assert np.array_equal(f1[j], f0[np.where(par)[0][0]])
         checked_copy += 1
     assert checked_mean > 10 and checked_copy > 10
+
+
+def test_sensor_vanishes_at_equilibrium():
+    """a state initialised at equilibrium has eps = 0 (to rounding) in every
+    cell that is not a ghost, NaN in the fine ghosts; a coarse ghost's
+    coalesced populations are means of its children's equilibria, close to
+    but not at its own equilibrium"""
+    w, o = vortex_oracle(levels=2)
+    eps = o.sensor()
+    e = o.export()
+    fg = (e["flags"] & F_FINE_GHOST) != 0
+    cg = (e["flags"] & F_COARSE_GHOST) != 0
+    assert np.all(np.isnan(eps[fg])) and not np.any(np.isnan(eps[~fg]))
+    assert np.max(eps[~fg & ~cg]) < 1e-14
+    assert np.max(eps[cg]) < 1e-4
+
+
+def test_sensor_flags_the_shock_of_a_sod_tube():
+    """after 10 steps of the D2Q21 Newton shock tube the cells above the
+    paper's threshold 0.2 sit at the exact Riemann shock (within 3 cells),
+    and those above 0.01 reach from the rarefaction head to past the shock
+    (its precursor)"""
+    import math
+    import riemann_exact  # noqa: F401  (the exact solver of the Sod pins)
+    w = W.sod(nx=256, ny=8, lattice="D2Q21", collision="DDF_NEWTON", theta=0.9, theta_at="right")
+    o = Oracle.from_workload(w)
+    o.init_workload(w)
+    steps = 10
+    o.step(steps)
+    eps = o.sensor()
+    e = o.export()
+    ok = ~np.isnan(eps)
+    xc = (e["coords"][:, 0] + 0.5) / 2.0 ** e["level"]
+    t = steps * math.sqrt(w.T0 / 0.8)  # exact-solution time (left state p = rho = 1)
+    xs = np.linspace(0.0, 256.0, 20001)
+    ex = riemann_exact.sample((xs - 128.0) / t, 1.0, 0.0, 1.0, 0.125, 0.0, 0.1, 1.4)
+    shock = xs[np.where(ex[0] > 0.126)[0].max()]  # last point above the right density
+    hot = ok & (eps > 0.2)
+    assert hot.sum() > 0
+    assert np.all(np.abs(xc[hot] - shock) < 3.0), (np.unique(np.round(xc[hot])), shock)
+    warm = ok & (eps > 0.01)
+    head = 128.0 - math.sqrt(1.4) * t
+    assert abs(xc[warm].min() - head) < 4.0 and xc[warm].max() > shock
