@@ -240,6 +240,15 @@ lbm_status lbm_profile_read(lbm_ctx *ctx, int level, int64_t *launches,
  * only, else may be NULL).  lbm_set_state restores such a state. */
 lbm_status lbm_get_state(lbm_ctx *ctx, double *f, double *g, double *lambda);
 
+/* Kinetic sensor of every cell at the synchronisation point (Eq.
+ * DeltaAvg): eps = mean over i of |f_i - f_eq,i| / |f_eq,i|, with f_eq the
+ * collision model's equilibrium at the cell's own moments (Newton
+ * warm-started from the stored multipliers, which are not changed), on f
+ * only; NaN for fine ghosts.  eps: host array [n_cells], canonical order.
+ * The paper refines where eps exceeds 0.2 (Sec. 8).  Errors: LBM_E_STATE
+ * without a state. */
+lbm_status lbm_sensor(lbm_ctx *ctx, double *eps);
+
 /* Mesh adaptation (Sec. 8, methodology of the adaptive runs): replaces the
  * grid by the one the new refinement masks (and solid masks, as in
  * lbm_grid_build; extent, level count and faces unchanged) describe, and

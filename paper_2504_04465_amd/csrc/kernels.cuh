@@ -1363,6 +1363,47 @@ __global__ void __launch_bounds__(BLOCK) k_init(const IArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// kinetic sensor of every cell at the synchronisation point (Eq. DeltaAvg):
+// the mean over i of |f_i - f_eq,i| / |f_eq,i|, f_eq of the collision model
+// at the cell's own moments (Newton warm-started from the stored
+// multipliers, which stay untouched); NaN for fine ghosts.  It is the
+// refinement criterion of mesh adaptation.
+// ---------------------------------------------------------------------------
+template <class L, int COLL, class S, bool PRE>
+__global__ void __launch_bounds__(BLOCK) k_sensor(const MArgs a, const PhysArgs ph) {
+  using C = typename Sto<S>::C;
+  constexpr int Q = L::Q;
+  constexpr bool DDF = COLL >= COLL_DDF_POLY;
+  __shared__ uint32_t nbs[BLOCK / 64][Brick<L>::NBP];
+  const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const bool live = t < a.count;  // whole wavefronts
+  const int64_t c = a.begin + (live ? t : 0);
+  const int32_t brick = stage_bricks<L, S>(a.topo, nbs, c, live);
+  const int32_t cell = live ? a.cell_of[c] : -1;
+  if (cell < 0) return;
+  if (a.flags[c] & F_FINE_GHOST) {
+    a.out[cell] = __longlong_as_double(0x7ff8000000000000ll);
+    return;
+  }
+  C f[Q];
+  C g[DDF ? Q : 1];
+  gather<L, S, PRE, DDF>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[threadIdx.x >> 6], a.stride, a.vbase, c,
+                         threadIdx.x & 63, brick, a.topo.xmask[brick], a.uw, a.cs2w, f, g);
+  C rho, u[3], T;
+  cell_moments<L, C, DDF>(f, g, (C)a.Cv, rho, u, T);
+  double lam[NLAM];
+#pragma unroll
+  for (int k = 0; k < NLAM; ++k) lam[k] = COLL >= COLL_DDF_NEWTON ? (double)a.lam[(int64_t)k * a.stride + c] : 0.0;
+  C feq[Q], geq[Q];
+  equilibrium_any<L, COLL, C>(rho, u, T, ph, lam, true, feq, geq);
+  constexpr C tiny = sizeof(C) == 8 ? (C)1e-300 : (C)1e-30;
+  C eps = (C)0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) eps += fabs(f[i] - feq[i]) / fmax(fabs(feq[i]), tiny);
+  a.out[cell] = (double)(eps * (C)(1.0 / Q));
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 inline unsigned nblocks(int64_t work) { return (unsigned)((work + BLOCK - 1) / BLOCK); }
@@ -1406,8 +1447,14 @@ struct Launch {
     if (a.n <= 0) return;
     hipLaunchKernelGGL((k_init<L, COLL, S>), dim3(nblocks(a.n)), dim3(BLOCK), 0, s, a);
   }
+  static void sensor(const MArgs &a, const PhysArgs &ph, bool pre, hipStream_t s) {
+    if (a.count <= 0) return;
+    if (pre) hipLaunchKernelGGL((k_sensor<L, COLL, S, true>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a, ph);
+    else hipLaunchKernelGGL((k_sensor<L, COLL, S, false>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a, ph);
+  }
   static Ops ops() {
     Ops o;
+    o.sensor = &sensor;
     o.collide = &collide;
     o.coalesce = &coalesce;
     o.explode = &explode;

@@ -750,6 +750,24 @@ lbm_status lbm_set_state(lbm_ctx *c, const double *f, const double *g, const dou
   return init_common(c, f, g, lambda, 1);
 }
 
+lbm_status lbm_sensor(lbm_ctx *c, double *eps) {
+  lbm_status s = need_state(c);
+  if (s != LBM_OK) return s;
+  if (!eps) return set_err(c, LBM_E_ARG, "null output");
+  double *d = scratch(c, sizeof(double) * (size_t)std::max<int64_t>(c->N, 1));
+  if (!d) return set_err(c, LBM_E_NOMEM, "scratch allocation failed");
+  coalesce_all(c);
+  for (int l = 0; l < c->L; ++l) {
+    MArgs a = gather_args(c, l, 0);
+    a.out = d;
+    c->ops.sensor(a, phys(c, l), c->pre[l], c->stream);
+  }
+  if ((s = check_launch(c)) != LBM_OK) return s;
+  HIP_TRY(c, hipMemcpyAsync(eps, d, sizeof(double) * c->N, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
 lbm_status lbm_remesh(lbm_ctx *c, const lbm_mask *refine, const lbm_mask *solid) {
   lbm_status s = need_state(c);
   if (s != LBM_OK) return s;

@@ -156,6 +156,7 @@ struct Ops {
   void (*bcfill)(const BArgs &, hipStream_t);
   void (*gather)(const MArgs &, bool pre, hipStream_t);
   void (*init)(const IArgs &, hipStream_t);
+  void (*sensor)(const MArgs &, const PhysArgs &, bool pre, hipStream_t);
   int sizeof_storage;
 };
 

@@ -28,7 +28,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_MASK", -3: "LBM_E_NOMEM", -4:
 EXPORTS = ["lbm_create", "lbm_grid_build", "lbm_grid_info", "lbm_layout_info", "lbm_grid_export", "lbm_init",
            "lbm_step", "lbm_set_face_bc", "lbm_set_graphs", "lbm_moments", "lbm_moments_device", "lbm_stats_get",
            "lbm_sync", "lbm_profile_enable", "lbm_profile_read", "lbm_get_state", "lbm_get_cells", "lbm_set_state",
-           "lbm_remesh",
+           "lbm_remesh", "lbm_sensor",
            "lbm_last_error", "lbm_destroy", "lbm_mlp_set_weights", "lbm_mlp_get_weights",
            "lbm_mlp_label", "lbm_mlp_predict", "lbm_mlp_grad", "lbm_mlp_train"]
 MLP_PARAMS = 9176
@@ -100,6 +100,7 @@ def lib():
         L.lbm_get_state.argtypes = [vp, vp, vp, vp]
         L.lbm_set_state.argtypes = [vp, vp, vp, vp]
         L.lbm_remesh.argtypes = [vp, vp, vp]
+        L.lbm_sensor.argtypes = [vp, vp]
         L.lbm_get_cells.argtypes = [vp, vp, i64, vp, vp, vp]
         L.lbm_last_error.restype = C.c_char_p
         L.lbm_last_error.argtypes = [vp]
@@ -238,6 +239,12 @@ class LBM:
                                            None if sa is None else C.cast(sa, C.c_void_p),
                                            C.cast(fa, C.c_void_p)), "lbm_grid_build")
         self._grid_info()
+
+    def sensor(self):
+        """kinetic sensor eps per cell (lbm_sensor), NaN for fine ghosts"""
+        out = np.zeros(self.n)
+        self._check(self._L.lbm_sensor(self.h, _ptr(out)), "lbm_sensor")
+        return out
 
     def remesh(self, refine, solid=None):
         """adapt the grid to new refinement (and solid) masks, moving the

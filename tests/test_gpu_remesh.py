@@ -47,3 +47,50 @@ def test_vortex_with_moving_patches(lattice, collision, storage, T0, tol):
     if collision == "DDF_NEWTON":
         assert st["newton_failures"] == 0
     s.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+def test_sensor_driven_adaptation_of_a_shock_tube(storage, tol):
+    """D2Q21 Newton shock tube whose refined patch follows the kinetic
+    sensor (threshold 0.2, Sec. 8): the device's sensor matches the
+    oracle's cell by cell, both adapt to the same masks (computed from the
+    oracle's sensor), and the runs agree at the end.  FP64: the sensor to
+    1e-9 absolute (it divides by small equilibrium populations), the moments
+    to steps x the 1e-12 Newton tolerance (measured 5e-11 and 6e-12); FP32:
+    the sensor to 1e-3 (its peak is ~1.4; measured 1.3e-5) and the moments
+    to 1e-4 (measured 1.6e-6)."""
+    from paper_2504_04465_amd import amr
+    w = W.sod(nx=256, ny=8, lattice="D2Q21", collision="DDF_NEWTON", theta=0.9, theta_at="right")
+    o = Oracle.from_workload(w)
+    s = B.LBM.from_workload(w, storage=storage)
+    coords, level = s.coords_levels()
+    m0 = w.initial_moments(coords, level)
+    o.init(m0)
+    s.init(m0)
+    steps = 0
+    for k in range(3):
+        o.step(8)
+        s.step(8)
+        steps += 8
+        eo, eg = o.sensor(), s.sensor()
+        assert np.array_equal(np.isnan(eo), np.isnan(eg))
+        ok = ~np.isnan(eo)
+        d = float(np.max(np.abs(eg[ok] - eo[ok])))
+        say(f"[amr] {storage} adaptation {k}: max |eps_gpu - eps_oracle| = {d:.3e}, max eps {np.max(eo[ok]):.3f}")
+        assert d < (1e-9 if storage == "fp64" else 1e-3)
+        e = o.export()
+        masks = amr.sensor_masks(eo, e["coords"], e["level"], w.ext, 2, threshold=0.2, grow=4)
+        remesh(o, masks)
+        s.remesh(masks)
+        c, lv = s.coords_levels()
+        assert np.array_equal(c, o.export()["coords"])
+    o.step(8)
+    s.step(8)
+    steps += 8
+    e = o.export()
+    err = compare(s.moments(), o.moments(), e["level"], 2)
+    say(f"[amr] {storage}: {err}")
+    bound = steps * w.newton_tol if storage == "fp64" else tol
+    assert err["u"] <= max(bound, 1e-12) and err["rho"] <= max(bound, 1e-12), err
+    assert s.stats()["newton_failures"] == 0
+    s.close()
