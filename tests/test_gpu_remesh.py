@@ -94,3 +94,35 @@ def test_sensor_driven_adaptation_of_a_shock_tube(storage, tol):
     assert err["u"] <= max(bound, 1e-12) and err["rho"] <= max(bound, 1e-12), err
     assert s.stats()["newton_failures"] == 0
     s.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-12), ("fp32", 1e-4)])
+def test_cube_patch_moved_in_3d(storage, tol):
+    """D3Q27 RR, periodic cube with a random velocity field and a cubic
+    refined patch moved twice (octree remesh: 8 children per coarsened cell)"""
+    n = 16
+    w = W.shear(n=n, levels=2, lattice="D3Q27", collision="RR", kind="random", u0=0.03, nu_finest=0.02)
+
+    def box(lo):
+        return [W._box_mask(w.ext, 3, 0, (lo, 5, 5), (lo + 6, 11, 11))]
+
+    w.refine = box(4)
+    o = Oracle.from_workload(w)
+    s = B.LBM.from_workload(w, storage=storage)
+    coords, level = s.coords_levels()
+    m0 = w.initial_moments(coords, level)
+    o.init(m0)
+    s.init(m0)
+    for lo in (5, 7):
+        o.step(3)
+        s.step(3)
+        remesh(o, box(lo))
+        s.remesh(box(lo))
+        c, lv = s.coords_levels()
+        assert np.array_equal(c, o.export()["coords"]) and np.array_equal(lv, o.export()["level"])
+    o.step(3)
+    s.step(3)
+    err = compare(s.moments(), o.moments(), o.export()["level"], 3)
+    say(f"[remesh] D3Q27 RR {storage}: {err}")
+    assert err["u"] <= tol and err["rho"] <= tol, err
+    s.close()
