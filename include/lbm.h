@@ -263,9 +263,10 @@ lbm_status lbm_sensor(lbm_ctx *ctx, double *eps);
  * is built on the host.  Cell numbering, layout and all device buffers are
  * replaced (re-read lbm_grid_info / lbm_grid_export); step and update
  * counts carry over, Newton / surrogate counters restart, surrogate
- * weights are kept.  Errors: LBM_E_STATE without a state, LBM_E_MASK for
- * inconsistent masks or a new fluid cell over old solid cells (the context
- * then has a grid and no state), LBM_E_NOMEM. */
+ * weights are kept.  Errors: LBM_E_STATE without a state; LBM_E_MASK for
+ * inconsistent masks (the context then has neither grid nor state) or for
+ * a new fluid cell over old solid cells (then it has the new grid and no
+ * state); LBM_E_NOMEM.  The old state is lost on any error. */
 lbm_status lbm_remesh(lbm_ctx *ctx, const lbm_mask *refine, const lbm_mask *solid);
 lbm_status lbm_set_state(lbm_ctx *ctx, const double *f, const double *g,
                          const double *lambda);

@@ -772,6 +772,11 @@ lbm_status lbm_remesh(lbm_ctx *c, const lbm_mask *refine, const lbm_mask *solid)
   lbm_status s = need_state(c);
   if (s != LBM_OK) return s;
   if (c->L > 1 && !refine) return set_err(c, LBM_E_ARG, "refine masks missing");
+  std::vector<float> mlpw;
+  if (c->have_mlp) {
+    mlpw.resize(MLP_PARAMS);
+    HIP_TRY(c, hipMemcpy(mlpw.data(), c->d_mlp_w, sizeof(float) * MLP_PARAMS, hipMemcpyDeviceToHost));
+  }
   // 1. the old tree's synchronisation-point state, canonical [rows][n_old],
   //    in a buffer of its own (the new grid releases the context's memory)
   const int Q = c->lat.Q;
@@ -803,11 +808,6 @@ lbm_status lbm_remesh(lbm_ctx *c, const lbm_mask *refine, const lbm_mask *solid)
   }
   // 2. the new tree: same extent, levels and faces
   HostGrid prev = std::move(c->g);
-  std::vector<float> mlpw;
-  if (c->have_mlp) {
-    mlpw.resize(MLP_PARAMS);
-    HIP_TRY(c, hipMemcpy(mlpw.data(), c->d_mlp_w, sizeof(float) * MLP_PARAMS, hipMemcpyDeviceToHost));
-  }
   lbm_face_bc faces[6];
   for (int k = 0; k < 6; ++k) faces[k] = c->face[k];
   const int64_t steps = c->coarse_steps;

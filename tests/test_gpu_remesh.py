@@ -126,3 +126,25 @@ def test_cube_patch_moved_in_3d(storage, tol):
     say(f"[remesh] D3Q27 RR {storage}: {err}")
     assert err["u"] <= tol and err["rho"] <= tol, err
     s.close()
+
+
+def test_remesh_keeps_surrogate_weights():
+    """a surrogate context keeps its network across a remesh and runs on"""
+    w = W.vortex(n=64, levels=2, lattice="D2Q21", collision="DDF_NEWTON", T0=0.65)
+    s = B.LBM(w.lattice, "DDF_MLP_NEWTON", "fp32", nu_finest=w.nu_finest, T0=w.T0, gamma=w.gamma,
+              newton_tol=w.newton_tol, newton_max_it=w.newton_max_it)
+    s.grid(w.dim, w.ext, w.n_levels, w.refine, w.solid, w.faces)
+    rng = np.random.default_rng(5)
+    wts = (0.05 * rng.standard_normal(B.MLP_PARAMS)).astype(np.float32)
+    s.mlp_set_weights(wts)
+    coords, level = s.coords_levels()
+    s.init(w.initial_moments(coords, level))
+    s.step(2)
+    s.remesh(w.patch(40))
+    assert np.array_equal(s.mlp_get_weights(), wts)
+    s.step(2)
+    st = s.stats()
+    assert st["newton_failures"] == 0 and st["newton_calls"] > 0
+    m = s.moments()
+    assert np.all(np.isfinite(m[:, ~np.isnan(m[0])]))
+    s.close()
