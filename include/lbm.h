@@ -102,6 +102,15 @@ typedef struct {
   int lambda_warm_start;   /* 1: start Newton from the stored multipliers    */
   int host_only;           /* 1: build the grid on the host only; no device
                               call is made and init/step return LBM_E_STATE  */
+  int in_place;            /* 1: stream in place on one population buffer
+                              (AA pattern: even steps read and write the
+                              cell's own rows, the opposite row for the
+                              result; odd steps pull from and push to the
+                              neighbours), half the population memory.  One
+                              level only, periodic / wall / moving-wall
+                              faces, no sponge, no surrogate; otherwise
+                              lbm_grid_build returns LBM_E_UNSUPPORTED.
+                              Results are identical to two buffers.      */
 } lbm_params;
 
 typedef struct {

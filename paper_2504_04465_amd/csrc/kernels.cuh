@@ -129,7 +129,10 @@ __device__ inline int lane_bits(int p, int d) {
 // Populations 1..Q-1 of cell c pulled through its explicit row: every
 // source is loaded before any is used, so the loads overlap.
 // Populations not in `want` (bit i) are neither loaded nor set.
-template <class L, class S, bool PRE, bool DDF>
+// AA = 2: the single in-place buffer after an even step holds cell x's
+// post-collision population i in row opp(i); pulls swap the rows (a wall
+// returns the cell's own row i).
+template <class L, class S, bool PRE, bool DDF, int AA = 0>
 __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnbr, int64_t xstride, int64_t row,
                                   int64_t stride, int64_t vbase, int64_t c, const double (&uw)[6][3], double cs2w,
                                   typename Sto<S>::C *f, typename Sto<S>::C *g, uint64_t want = ~0ull) {
@@ -142,8 +145,9 @@ __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnb
     if (!((want >> i) & 1ull)) continue;
     const int32_t s = sv[i];
     int64_t idx;
+    const int ri = AA == 2 ? L::S.opp[i] : i, ro = AA == 2 ? i : L::S.opp[i];
     if (PRE) idx = (int64_t)i * stride + ((int64_t)s >= vbase ? (int64_t)s : c);
-    else idx = s >= 0 ? (int64_t)i * stride + s : (int64_t)L::S.opp[i] * stride + c;
+    else idx = s >= 0 ? (int64_t)ri * stride + s : (int64_t)ro * stride + c;
     // the lattice is symmetric: w of the opposite population is w_i
     f[i] = Sto<S>::ld(fin, idx, L::S.w[i]);
     if (DDF) g[i] = Sto<S>::ld(gin, idx, 0.0);
@@ -168,7 +172,7 @@ __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnb
 //
 // Lanes flagged in the brick's exception mask read their explicit row:
 // every source is loaded before any is used, so the loads overlap.
-template <class L, class S, bool PRE, bool DDF>
+template <class L, class S, bool PRE, bool DDF, int AA = 0>
 __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const uint32_t *nbs, int64_t stride,
                               int64_t vbase, int64_t c, int lane, int32_t brick, uint64_t xm,
                               const double (&uw)[6][3], double cs2w, typename Sto<S>::C *f,
@@ -209,18 +213,79 @@ __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const 
     for (int i = 1; i < L::Q; ++i) {
       const uint32_t k = K[0][cx_<L>(i, 0) + R] + K[1][cx_<L>(i, 1) + R] + K[2][cx_<L>(i, 2) + R];
       const uint32_t off = nbs[k >> 18] + (k & 0xffffu);
-      f[i] = Sto<S>::ldv(*(const S *)(fb + i * pstride + off), L::S.w[i]);
-      if (DDF) g[i] = Sto<S>::ldv(*(const S *)(gb + i * pstride + off), 0.0);
+      const int64_t ri = AA == 2 ? L::S.opp[i] : i;
+      f[i] = Sto<S>::ldv(*(const S *)(fb + ri * pstride + off), L::S.w[i]);
+      if (DDF) g[i] = Sto<S>::ldv(*(const S *)(gb + ri * pstride + off), 0.0);
     }
   } else {
     const int64_t row = tp.xbase[brick] + __popcll(xm & ((1ull << lane) - 1ull));
-    gather_row<L, S, PRE, DDF>(fin, gin, tp.xnbr, tp.xstride, row, stride, vbase, c, uw, cs2w, f, g);
+    gather_row<L, S, PRE, DDF, AA>(fin, gin, tp.xnbr, tp.xstride, row, stride, vbase, c, uw, cs2w, f, g);
+  }
+}
+
+// In-place (AA-pattern) store after an odd step: population i of cell x goes
+// to row i of x + xi_i (the cell whose pull of i reads x), or, where that is a
+// wall, back to the cell's own row opp(i) with the moving-wall correction of
+// population opp(i) (the bounce-back the next pull would have applied).
+template <class L, class S, bool DDF>
+__device__ inline void push_store(S *fout, S *gout, const Topo &tp, const uint32_t *nbs, int64_t stride, int64_t c,
+                                  int lane, int32_t brick, uint64_t xm, const double (&uw)[6][3], double cs2w,
+                                  const typename Sto<S>::C *f, const typename Sto<S>::C *g) {
+  using C = typename Sto<S>::C;
+  constexpr int BS = Brick<L>::BS, R = L::B, D = L::D;
+  Sto<S>::stn(fout, c, f[0], L::S.w[0]);
+  if (DDF) Sto<S>::stn(gout, c, g[0], 0.0);
+  if (!((xm >> lane) & 1ull)) {
+    uint32_t K[3][2 * R + 1];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int lc = d < D ? lane_coord<L>(lane, d) : 0;
+#pragma unroll
+      for (int x = -R; x <= R; ++x) {
+        if (d >= D) {
+          K[d][x + R] = 0u;
+          continue;
+        }
+        const int p = lc - x;
+        const uint32_t w = p < 0 ? 0u : (p >= BS ? 2u : 1u);
+        const uint32_t pw = d == 0 ? 1u : (d == 1 ? 3u : 9u);
+        K[d][x + R] = ((w * pw * 4u) << 16) | ((uint32_t)lane_bits<L>(p & (BS - 1), d) * (uint32_t)sizeof(S));
+      }
+    }
+    char *fb = (char *)fout;
+    char *gb = (char *)gout;
+    const int64_t pstride = stride * (int64_t)sizeof(S);
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+      // x + xi_i is the pull source of the opposite population
+      const int j = L::S.opp[i];
+      const uint32_t k = K[0][cx_<L>(j, 0) + R] + K[1][cx_<L>(j, 1) + R] + K[2][cx_<L>(j, 2) + R];
+      const uint32_t off = nbs[k >> 18] + (k & 0xffffu);
+      Sto<S>::stn((S *)(fb + i * pstride + off), 0, f[i], L::S.w[i]);
+      if (DDF) Sto<S>::stn((S *)(gb + i * pstride + off), 0, g[i], 0.0);
+    }
+  } else {
+    const int64_t row = tp.xbase[brick] + __popcll(xm & ((1ull << lane) - 1ull));
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+      const int j = L::S.opp[i];
+      const int32_t s = tp.xnbr[(int64_t)(j - 1) * tp.xstride + row];
+      if (s >= 0) {
+        Sto<S>::stn(fout, (int64_t)i * stride + s, f[i], L::S.w[i]);
+        if (DDF) Sto<S>::stn(gout, (int64_t)i * stride + s, g[i], 0.0);
+      } else {
+        C v = f[i];
+        if (s <= -2) v += (C)(2.0 * L::S.w[j] * wall_dot<L>(uw, -2 - s, j) / cs2w);
+        Sto<S>::stn(fout, (int64_t)j * stride + c, v, L::S.w[j]);
+        if (DDF) Sto<S>::stn(gout, (int64_t)j * stride + c, g[i], 0.0);
+      }
+    }
   }
 }
 
 // Gather for one cell anywhere (no brick per wavefront): the neighbour
 // brick ids come straight from the table.  Used by the sampled read-back.
-template <class L, class S, bool PRE, bool DDF>
+template <class L, class S, bool PRE, bool DDF, int AA = 0>
 __device__ inline void gather_one(const S *fin, const S *gin, const Topo &tp, int64_t stride, int64_t vbase,
                                   int64_t c, const double (&uw)[6][3], double cs2w, typename Sto<S>::C *f,
                                   typename Sto<S>::C *g) {
@@ -229,7 +294,7 @@ __device__ inline void gather_one(const S *fin, const S *gin, const Topo &tp, in
   const int lane = (int)(c & 63);
   const uint64_t xm = tp.xmask[brick];
   if ((xm >> lane) & 1ull) {
-    gather<L, S, PRE, DDF>(fin, gin, tp, nullptr, stride, vbase, c, lane, (int32_t)brick, xm, uw, cs2w, f, g);
+    gather<L, S, PRE, DDF, AA>(fin, gin, tp, nullptr, stride, vbase, c, lane, (int32_t)brick, xm, uw, cs2w, f, g);
     return;
   }
   f[0] = Sto<S>::ld(fin, c, L::S.w[0]);
@@ -249,8 +314,9 @@ __device__ inline void gather_one(const S *fin, const S *gin, const Topo &tp, in
       }
       src = (int64_t)tp.nbrick[brick * Brick<L>::NBP + dir] * 64 + loc;
     }
-    f[i] = Sto<S>::ld(fin, (int64_t)i * stride + src, L::S.w[i]);
-    if (DDF) g[i] = Sto<S>::ld(gin, (int64_t)i * stride + src, 0.0);
+    const int64_t ri = AA == 2 ? L::S.opp[i] : i;
+    f[i] = Sto<S>::ld(fin, ri * stride + src, L::S.w[i]);
+    if (DDF) g[i] = Sto<S>::ld(gin, ri * stride + src, 0.0);
   }
 }
 
@@ -908,7 +974,10 @@ struct CollideBlock {
   static constexpr int value = (L::D == 3 && COLL < COLL_DDF_POLY) ? 512 : BLOCK;
 };
 
-template <class L, int COLL, class S, bool PRE>
+// AA selects in-place streaming on one buffer (a.fin == a.fout): 1 = even
+// step (read the cell's own rows, write population i to its row opp(i)),
+// 2 = odd step (pull from the swapped rows, push to the neighbours).
+template <class L, int COLL, class S, bool PRE, int AA = 0>
 __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
     __attribute__((amdgpu_waves_per_eu(MinWaves<L, COLL, S>::value))) k_collide(const KArgs a) {
   using C = typename Sto<S>::C;
@@ -928,8 +997,9 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
   const S *gin = (const S *)a.gin;
   C f[Q];
   C g[DDF ? Q : 1];
-  gather<L, S, PRE, DDF>(fin, gin, a.topo, nbs[threadIdx.x >> 6], stride, a.vbase, c, threadIdx.x & 63, brick,
-                         a.topo.xmask[brick], a.ph.uw, a.ph.cs2w, f, g);
+  gather<L, S, PRE || AA == 1, DDF, AA == 2 ? 2 : 0>(fin, gin, a.topo, nbs[threadIdx.x >> 6], stride, a.vbase, c,
+                                                   threadIdx.x & 63, brick, a.topo.xmask[brick], a.ph.uw,
+                                                   a.ph.cs2w, f, g);
   if (!(fl & (F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ))) {
     C rho, u[3], T;
     cell_moments<L, C, DDF>(f, g, (C)a.ph.Cv, rho, u, T);
@@ -1017,10 +1087,16 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
   }
   S *fout = (S *)a.fout;
   S *gout = (S *)a.gout;
+  if constexpr (AA == 2) {
+    push_store<L, S, DDF>(fout, gout, a.topo, nbs[threadIdx.x >> 6], stride, c, threadIdx.x & 63, brick,
+                          a.topo.xmask[brick], a.ph.uw, a.ph.cs2w, f, g);
+  } else {
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    Sto<S>::stn(fout, (int64_t)i * stride + c, f[i], L::S.w[i]);
-    if (DDF) Sto<S>::stn(gout, (int64_t)i * stride + c, g[i], 0.0);
+    for (int i = 0; i < Q; ++i) {
+      const int64_t r = AA == 1 ? L::S.opp[i] : i;
+      Sto<S>::stn(fout, r * stride + c, f[i], L::S.w[i]);
+      if (DDF) Sto<S>::stn(gout, r * stride + c, g[i], 0.0);
+    }
   }
 }
 
@@ -1223,7 +1299,7 @@ __global__ void __launch_bounds__(BLOCK) k_bcfill(const BArgs a) {
 // gathers of the synchronisation-point state (pre-collision populations;
 // coarse ghosts read their coalesced slots)
 // ---------------------------------------------------------------------------
-template <class L, class S, bool PRE, bool DDF>
+template <class L, class S, bool PRE, bool DDF, int AA = 0>
 __global__ void __launch_bounds__(BLOCK) k_gather(const MArgs a) {
   using C = typename Sto<S>::C;
   constexpr int Q = L::Q;
@@ -1237,7 +1313,8 @@ __global__ void __launch_bounds__(BLOCK) k_gather(const MArgs a) {
     const int64_t c = a.slot_of[cell];
     C f[Q];
     C g[DDF ? Q : 1];
-    gather_one<L, S, PRE, DDF>((const S *)a.fin, (const S *)a.gin, a.topo, a.stride, a.vbase, c, a.uw, a.cs2w, f, g);
+    gather_one<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, a.stride, a.vbase, c, a.uw, a.cs2w,
+                                   f, g);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       a.out[(int64_t)i * a.n + k] = (double)f[i];
@@ -1256,8 +1333,8 @@ __global__ void __launch_bounds__(BLOCK) k_gather(const MArgs a) {
   C g[DDF ? Q : 1];
   const bool fine_ghost = valid && (a.flags[c] & F_FINE_GHOST);
   if (valid)
-    gather<L, S, PRE, DDF>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[threadIdx.x >> 6], a.stride, a.vbase,
-                           c, threadIdx.x & 63, brick, a.topo.xmask[brick], a.uw, a.cs2w, f, g);
+    gather<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[threadIdx.x >> 6], a.stride,
+                               a.vbase, c, threadIdx.x & 63, brick, a.topo.xmask[brick], a.uw, a.cs2w, f, g);
   if (a.mode == 0) {
     if (!valid) return;
     const int nm = 1 + L::D + (DDF ? 1 : 0);
@@ -1369,7 +1446,7 @@ __global__ void __launch_bounds__(BLOCK) k_init(const IArgs a) {
 // multipliers, which stay untouched); NaN for fine ghosts.  It is the
 // refinement criterion of mesh adaptation.
 // ---------------------------------------------------------------------------
-template <class L, int COLL, class S, bool PRE>
+template <class L, int COLL, class S, bool PRE, int AA = 0>
 __global__ void __launch_bounds__(BLOCK) k_sensor(const MArgs a, const PhysArgs ph) {
   using C = typename Sto<S>::C;
   constexpr int Q = L::Q;
@@ -1387,8 +1464,8 @@ __global__ void __launch_bounds__(BLOCK) k_sensor(const MArgs a, const PhysArgs 
   }
   C f[Q];
   C g[DDF ? Q : 1];
-  gather<L, S, PRE, DDF>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[threadIdx.x >> 6], a.stride, a.vbase, c,
-                         threadIdx.x & 63, brick, a.topo.xmask[brick], a.uw, a.cs2w, f, g);
+  gather<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[threadIdx.x >> 6], a.stride, a.vbase,
+                             c, threadIdx.x & 63, brick, a.topo.xmask[brick], a.uw, a.cs2w, f, g);
   C rho, u[3], T;
   cell_moments<L, C, DDF>(f, g, (C)a.Cv, rho, u, T);
   double lam[NLAM];
@@ -1416,7 +1493,9 @@ struct Launch {
     if (a.count <= 0) return;
     constexpr int CB = CollideBlock<L, COLL>::value;
     const unsigned nb = (unsigned)((a.count + CB - 1) / CB);
-    if (pre) hipLaunchKernelGGL((k_collide<L, COLL, S, true>), dim3(nb), dim3(CB), 0, s, a);
+    if (a.aa == 1) hipLaunchKernelGGL((k_collide<L, COLL, S, false, 1>), dim3(nb), dim3(CB), 0, s, a);
+    else if (a.aa == 2) hipLaunchKernelGGL((k_collide<L, COLL, S, false, 2>), dim3(nb), dim3(CB), 0, s, a);
+    else if (pre) hipLaunchKernelGGL((k_collide<L, COLL, S, true>), dim3(nb), dim3(CB), 0, s, a);
     else hipLaunchKernelGGL((k_collide<L, COLL, S, false>), dim3(nb), dim3(CB), 0, s, a);
   }
   static void coalesce(const CArgs &a0, bool pre, hipStream_t s) {
@@ -1440,7 +1519,8 @@ struct Launch {
   }
   static void gather(const MArgs &a, bool pre, hipStream_t s) {
     if (a.count <= 0) return;
-    if (pre) hipLaunchKernelGGL((k_gather<L, S, true, DDF>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
+    if (a.aa == 2) hipLaunchKernelGGL((k_gather<L, S, false, DDF, 2>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
+    else if (pre) hipLaunchKernelGGL((k_gather<L, S, true, DDF>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
     else hipLaunchKernelGGL((k_gather<L, S, false, DDF>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
   }
   static void init(const IArgs &a, hipStream_t s) {
@@ -1449,7 +1529,9 @@ struct Launch {
   }
   static void sensor(const MArgs &a, const PhysArgs &ph, bool pre, hipStream_t s) {
     if (a.count <= 0) return;
-    if (pre) hipLaunchKernelGGL((k_sensor<L, COLL, S, true>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a, ph);
+    if (a.aa == 2)
+      hipLaunchKernelGGL((k_sensor<L, COLL, S, false, 2>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a, ph);
+    else if (pre) hipLaunchKernelGGL((k_sensor<L, COLL, S, true>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a, ph);
     else hipLaunchKernelGGL((k_sensor<L, COLL, S, false>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a, ph);
   }
   static Ops ops() {

@@ -65,6 +65,8 @@ struct lbm_ctx {
   size_t scratch_bytes = 0;
   int parity[8]{};
   bool pre[8]{};
+  int aa_state = 0;  // in-place streaming: 0 own rows hold f_in, 1 rows swapped (after an even step)
+  int gaa = 0;
   bool have_state = false;
   int64_t updates[8]{};
   int64_t coarse_steps = 0;
@@ -307,6 +309,10 @@ void launch_collide(lbm_ctx *c, int l) {
       slot.level = l;
       hipEventRecord(slot.a, c->stream);
     }
+    if (c->p.in_place) {
+      a.aa = c->aa_state == 0 ? 1 : 2;
+      c->aa_state ^= 1;
+    }
     c->ops.collide(a, c->pre[l], c->stream);
     if (c->prof) {
       hipEventRecord(slot.b, c->stream);
@@ -361,8 +367,13 @@ void coalesce_all(lbm_ctx *c) {
   for (int l = 0; l + 1 < c->L; ++l) launch_coalesce(c, l);
 }
 
+// readers of the synchronisation-point state: own rows (pre-collision at
+// start, or the in-place buffer after an odd step), or swapped pulls
+bool read_pre(const lbm_ctx *c, int l) { return c->pre[l] || (c->p.in_place && c->aa_state == 0); }
+
 MArgs gather_args(lbm_ctx *c, int l, int mode) {
   MArgs a{};
+  a.aa = c->p.in_place && c->aa_state == 1 ? 2 : 0;
   a.fin = fbuf(c, l);
   a.gin = gbuf(c, l);
   a.lam = c->d_lam;
@@ -549,6 +560,16 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
       c->bpu[l] = ncell > 0 ? pops + tables / (double)ncell : pops;
     }
   }
+  if (c->p.in_place) {
+    // one buffer streamed in place: single level, faces without post-collision fills
+    bool ok = n_levels == 1 && c->lat.kind >= 0 && c->p.collision <= LBM_DDF_NEWTON;
+    for (int k = 0; k < 6; ++k)
+      ok = ok && (faces[k].kind == LBM_BC_PERIODIC || faces[k].kind == LBM_BC_WALL ||
+                  faces[k].kind == LBM_BC_MOVING_WALL) && faces[k].sponge_sigma_max <= 0.0;
+    if (!ok)
+      return set_err(c, LBM_E_UNSUPPORTED,
+                     "in-place streaming needs one level, periodic / wall faces, no sponge, no surrogate");
+  }
   c->have_grid = true;
   if (c->p.host_only) return LBM_OK;
   // ---- device upload ----------------------------------------------------
@@ -559,6 +580,11 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
   // bulk gathers address a population array with 32-bit byte offsets
   if ((double)NS * (double)ssz >= 4294967296.0) return set_err(c, LBM_E_ARG, "grid too large for 32-bit offsets");
   for (int b = 0; b < 2; ++b) {
+    if (b == 1 && c->p.in_place) {
+      c->f[1] = c->f[0];
+      c->gb[1] = c->gb[0];
+      break;
+    }
     c->f[b] = dev_alloc(c, ssz * Q * c->stride);
     if (!c->f[b]) return set_err(c, LBM_E_NOMEM, "population allocation failed");
     if (c->ddf) {
@@ -730,6 +756,7 @@ static lbm_status init_common(lbm_ctx *c, const double *src, const double *src_g
   for (int l = 0; l < c->L; ++l) {
     c->parity[l] = 0;
     c->pre[l] = true;
+    c->aa_state = 0;
     c->updates[l] = 0;
   }
   c->coarse_steps = 0;
@@ -760,7 +787,7 @@ lbm_status lbm_sensor(lbm_ctx *c, double *eps) {
   for (int l = 0; l < c->L; ++l) {
     MArgs a = gather_args(c, l, 0);
     a.out = d;
-    c->ops.sensor(a, phys(c, l), c->pre[l], c->stream);
+    c->ops.sensor(a, phys(c, l), read_pre(c, l), c->stream);
   }
   if ((s = check_launch(c)) != LBM_OK) return s;
   HIP_TRY(c, hipMemcpyAsync(eps, d, sizeof(double) * c->N, hipMemcpyDeviceToHost, c->stream));
@@ -771,6 +798,7 @@ lbm_status lbm_sensor(lbm_ctx *c, double *eps) {
 lbm_status lbm_remesh(lbm_ctx *c, const lbm_mask *refine, const lbm_mask *solid) {
   lbm_status s = need_state(c);
   if (s != LBM_OK) return s;
+  if (c->p.in_place) return set_err(c, LBM_E_UNSUPPORTED, "in-place streaming runs on one level only");
   if (c->L > 1 && !refine) return set_err(c, LBM_E_ARG, "refine masks missing");
   std::vector<float> mlpw;
   if (c->have_mlp) {
@@ -800,7 +828,7 @@ lbm_status lbm_remesh(lbm_ctx *c, const lbm_mask *refine, const lbm_mask *solid)
     MArgs a = gather_args(c, l, 1);
     a.out = old;
     a.lam_out = c->lamf ? old + (size_t)pop_rows * n_old : nullptr;
-    c->ops.gather(a, c->pre[l], c->stream);
+    c->ops.gather(a, read_pre(c, l), c->stream);
   }
   if ((s = check_launch(c)) != LBM_OK) {
     release_old();
@@ -894,10 +922,11 @@ bool graph_ready(lbm_ctx *c) {
   if (c->gexec) {
     bool same = true;
     for (int l = 0; l < c->L; ++l) same = same && c->gparity[l] == c->parity[l];
-    if (same) return true;
+    if (same && c->gaa == c->aa_state) return true;
     drop_graph(c);
   }
   int par[8];
+  const int aa = c->aa_state;
   int64_t upd[8], cs = c->coarse_steps;
   for (int l = 0; l < 8; ++l) {
     par[l] = c->parity[l];
@@ -913,6 +942,7 @@ bool graph_ready(lbm_ctx *c) {
     c->updates[l] = upd[l];
   }
   c->coarse_steps = cs;
+  c->aa_state = aa;
   if (e != hipSuccess || !g) {
     hipGetLastError();
     return false;
@@ -926,6 +956,7 @@ bool graph_ready(lbm_ctx *c) {
   }
   c->gexec = x;
   for (int l = 0; l < c->L; ++l) c->gparity[l] = c->parity[l];
+  c->gaa = c->aa_state;
   return true;
 }
 
@@ -974,7 +1005,7 @@ lbm_status lbm_moments_device(lbm_ctx *c, double *out_dev) {
   for (int l = 0; l < c->L; ++l) {
     MArgs a = gather_args(c, l, 0);
     a.out = out_dev;
-    c->ops.gather(a, c->pre[l], c->stream);
+    c->ops.gather(a, read_pre(c, l), c->stream);
   }
   return check_launch(c);
 }
@@ -1005,7 +1036,7 @@ lbm_status lbm_get_state(lbm_ctx *c, double *f, double *g, double *lambda) {
     MArgs a = gather_args(c, l, 1);
     a.out = d;
     a.lam_out = c->lamf ? d + rows * c->N : nullptr;
-    c->ops.gather(a, c->pre[l], c->stream);
+    c->ops.gather(a, read_pre(c, l), c->stream);
   }
   if ((s = check_launch(c)) != LBM_OK) return s;
   HIP_TRY(c, hipMemcpyAsync(f, d, sizeof(double) * Q * c->N, hipMemcpyDeviceToHost, c->stream));
@@ -1061,7 +1092,7 @@ lbm_status lbm_get_cells(lbm_ctx *c, const int64_t *cells, int64_t n, double *f,
     a.n = n;
     a.out = d;
     a.lam_out = c->lamf ? d + rows * n : nullptr;
-    c->ops.gather(a, c->pre[l], c->stream);
+    c->ops.gather(a, read_pre(c, l), c->stream);
   }
   if ((s = check_launch(c)) != LBM_OK) return s;
   std::vector<double> h(need - (n + 1) / 2);
@@ -1095,7 +1126,7 @@ lbm_status lbm_stats_get(lbm_ctx *c, lbm_stats *out) {
   for (int l = 0; l < c->L; ++l) {
     MArgs a = gather_args(c, l, 2);
     a.partials = d + 6 * boff[l];
-    c->ops.gather(a, c->pre[l], c->stream);
+    c->ops.gather(a, read_pre(c, l), c->stream);
   }
   if ((s = check_launch(c)) != LBM_OK) return s;
   std::vector<double> h(6 * std::max<int64_t>(boff[c->L], 1));

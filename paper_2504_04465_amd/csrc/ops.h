@@ -65,6 +65,7 @@ struct KArgs {
   int64_t begin, count;
   PhysArgs ph;
   unsigned long long *counters;
+  int aa;              // in-place streaming: 0 off, 1 even step, 2 odd step
 };
 
 // coalescence of the unknown populations of one level's coarse ghosts
@@ -133,6 +134,7 @@ struct MArgs {
   int64_t n;
   double vol;          // cell volume 2^(-D l) for sums
   double *partials;    // [blocks][6]
+  int aa;              // 2: in-place buffer after an even step (rows swapped)
 };
 
 // initialisation from moments, or restore of a raw state

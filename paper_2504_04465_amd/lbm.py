@@ -45,7 +45,7 @@ class Params(C.Structure):
                 ("nu_finest", C.c_double), ("T0", C.c_double), ("gamma", C.c_double),
                 ("sensor_A", C.c_double), ("sensor_on", C.c_int), ("trace_equilibration", C.c_int),
                 ("newton_tol", C.c_double), ("fallback_tol", C.c_double), ("newton_max_it", C.c_int),
-                ("lambda_warm_start", C.c_int), ("host_only", C.c_int)]
+                ("lambda_warm_start", C.c_int), ("host_only", C.c_int), ("in_place", C.c_int)]
 
 
 class FaceBC(C.Structure):
@@ -175,11 +175,11 @@ class LBM:
                  T0: float = 0.0, gamma: float = 1.4, sensor_A: float = 1.5, sensor_on: bool = False,
                  trace_eq: bool = False, newton_tol: float = 1e-12, fallback_tol: float = 1e-10,
                  newton_max_it: int = 100, warm_start: bool = True, host_only: bool = False,
-                 device: int = 0, stream=None):
+                 in_place: bool = False, device: int = 0, stream=None):
         self._L = lib()
         p = Params(LATTICES[lattice], COLLISIONS[collision], STORAGE[storage], nu_finest, T0, gamma,
                    sensor_A, int(sensor_on), int(trace_eq), newton_tol, fallback_tol, newton_max_it,
-                   int(warm_start), int(host_only))
+                   int(warm_start), int(host_only), int(in_place))
         self.lattice, self.collision, self.storage = lattice, collision, storage
         self.ddf = collision.startswith("DDF")
         self.host_only = host_only

@@ -146,3 +146,18 @@ def test_brick_layout_uniform_periodic_needs_no_rows():
     # wrap columns / rows: the last brick is half empty, so cells within one
     # cell of the wrap in x or y take rows: 20 * 20 - 18 * 18 = 76
     assert rows == 20 * 20 - 18 * 18
+
+
+def test_in_place_streaming_limits():
+    """in-place streaming is refused for refined grids and open faces"""
+    w = W.shear(n=16, levels=2, lattice="D2Q9", collision="RR")
+    with pytest.raises(B.LbmError) as e:
+        B.LBM.from_workload(w, host_only=True, in_place=True)
+    assert e.value.code == -7
+    w = W.cavity(n=16, levels=1)
+    w.faces[0] = W.Face("neumann")
+    with pytest.raises(B.LbmError) as e:
+        B.LBM.from_workload(w, host_only=True, in_place=True)
+    assert e.value.code == -7
+    s = B.LBM.from_workload(W.cavity(n=16, levels=1), host_only=True, in_place=True)
+    assert s.n == 256
