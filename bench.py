@@ -315,6 +315,8 @@ def main():
     ap.add_argument("--workload", default="sphere")
     ap.add_argument("--storage", default=None)
     ap.add_argument("--lattice", default=None, help="lattice of the cavity_uniform / sod_newton workloads")
+    ap.add_argument("--in-place", action="store_true",
+                    help="stream in place on one population buffer (single-level workloads)")
     ap.add_argument("--scale", type=int, default=1)
     ap.add_argument("--cpu-scale", type=int, default=4)
     ap.add_argument("--cpu-steps", type=int, default=60)
@@ -350,7 +352,8 @@ def main():
     w = workload(args.workload, args.scale, args.storage, args.lattice)
     storage = args.storage or w.storage
     t0 = time.perf_counter()
-    s = B.LBM.from_workload(w, storage=storage)
+    torch.cuda.reset_peak_memory_stats()
+    s = B.LBM.from_workload(w, storage=storage, in_place=args.in_place)
     t_build = time.perf_counter() - t0
     s.init_workload(w)
     print(f"[bench] {describe(w, storage)}: {s.n} cells {list(s.n_per_level)}, grid {t_build:.1f} s",
@@ -441,6 +444,8 @@ def main():
         "mlups_paper_formula": round(s.n * args.steps * (1 << (L - 1)) / (dt_graph or dt) / 1e6, 2),
         "launch": "HIP graph per pair of coarse steps" if dt_graph is not None else "kernel launches",
         "paper_a100_mlups": PAPER_A100_MLUPS.get((args.workload, w.lattice, storage)) if args.scale == 1 else None,
+        "streaming": "in place, one buffer" if args.in_place else "two buffers",
+        "device_memory_gb": round(torch.cuda.max_memory_allocated() / 1e9, 2),
         "newton": {"calls": st["newton_calls"], "iterations": st["newton_iterations"],
                    "failures": st["newton_failures"]},
     }
