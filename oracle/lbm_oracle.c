@@ -641,7 +641,7 @@ ol_sim *ol_create(const ol_params *p) {
   int lat = p->lattice, coll = p->collision;
   int ok = (lat != OL_D2Q37 && (coll == OL_BGK || coll == OL_RR)) ||
            (lat == OL_D2Q37 && coll == OL_DDF_POLY) ||
-           ((lat == OL_D2Q21 || lat == OL_D2Q13) && coll == OL_DDF_NEWTON);
+           ((lat == OL_D2Q21 || lat == OL_D2Q13 || lat == OL_D2Q37) && coll == OL_DDF_NEWTON);
   if (!ok) { free(s); return NULL; }
   return s;
 }

@@ -277,6 +277,7 @@ def newton_residual(o, u, T, lam):
 NEWTON_STATES = {
     "D2Q21": (0.65, [((0.3, -0.2), 0.65), ((1.43, 0.0), 0.65), ((0.0, 0.0), 0.9), ((0.5, 0.7), 0.5)]),
     "D2Q13": (0.35, [((0.3, -0.2), 0.35), ((0.8, 0.0), 0.35), ((0.0, 0.0), 0.5), ((0.3, 0.4), 0.3)]),
+    "D2Q37": (1.0, [((0.3, -0.2), 1.0), ((2.0, 0.0), 1.0), ((0.0, 0.0), 1.3), ((0.9, 1.1), 0.8)]),
 }
 
 

@@ -304,7 +304,7 @@ def test_sod_against_exact_riemann():
     assert np.nanmin(m[0]) > 0.12 and np.nanmax(m[0]) < 1.001
 
 
-@pytest.mark.parametrize("lattice,theta", [("D2Q13", 0.35), ("D2Q21", 0.9)])
+@pytest.mark.parametrize("lattice,theta", [("D2Q13", 0.35), ("D2Q21", 0.9), ("D2Q37", 1.0)])
 def test_sod_numerical_equilibrium_against_exact_riemann(lattice, theta):
     """The same inviscid shock tube with the double-distribution Newton
     equilibrium on D2Q13 and D2Q21 at the paper's inviscid reference
