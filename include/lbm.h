@@ -60,7 +60,8 @@ enum { LBM_D2Q9 = 0, LBM_D3Q27 = 1, LBM_D2Q21 = 2, LBM_D2Q37 = 3, LBM_D2Q13 = 4 
  *   DDF_POLY       double distribution, fourth-order thermal polynomial
  *                  equilibrium, g_eq of Eq. gEq, BGK on f and g (D2Q37)
  *   DDF_NEWTON     double distribution, numerical equilibrium Eq. exponential
- *                  solved by Newton on the eight constraints (D2Q21, D2Q13)
+ *                  solved by Newton on the eight constraints (D2Q21, D2Q13,
+ *                  D2Q37)
  *   DDF_MLP        as DDF_NEWTON, multipliers predicted by the MLP only
  *   DDF_MLP_NEWTON MLP prediction + one Newton step, full Newton wherever the
  *                  constraint residual still exceeds fallback_tol            */

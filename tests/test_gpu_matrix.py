@@ -24,6 +24,7 @@ COMBOS = ([(lat, coll, sto) for lat in ("D2Q9", "D3Q27") for coll in ("BGK", "RR
           + [("D2Q37", "DDF_POLY", sto) for sto in ("fp64", "fp32")]
           + [("D2Q21", "DDF_NEWTON", sto) for sto in ("fp64", "fp32")]
           + [("D2Q13", "DDF_NEWTON", sto) for sto in ("fp64", "fp32")]
+          + [("D2Q37", "DDF_NEWTON", sto) for sto in ("fp64", "fp32")]
           + [(lat, coll, sto) for lat in ("D2Q13", "D2Q21") for coll in ("BGK", "RR")
              for sto in ("fp64", "fp32", "fp16")])
 

@@ -79,7 +79,7 @@ def test_sod_d2q37(storage, tol):
         say("[parity] sod fp32 largest |drho| at x =", np.round(xc[order], 2), "values", d[order])
 
 
-@pytest.mark.parametrize("lattice,theta", [("D2Q13", 0.35), ("D2Q21", 0.9)])
+@pytest.mark.parametrize("lattice,theta", [("D2Q13", 0.35), ("D2Q21", 0.9), ("D2Q37", 1.0)])
 @pytest.mark.parametrize("storage,tol", [("fp64", None), ("fp32", 5e-3)])
 def test_sod_newton(lattice, theta, storage, tol):
     """Shock tube with the Newton numerical equilibrium on D2Q13 / D2Q21,
