@@ -1343,6 +1343,34 @@ int ol_sums(ol_sim *s, double *out) {
   return 0;
 }
 
+/* kinetic energy of the synchronisation-point state (the monitor of the
+ * paper's convergence test, Sec. 5.2): sum over the cells that are not fine
+ * ghosts of 2^(-D l) rho |u|^2 / 2, with rho and u the moments of the cell */
+int ol_kinetic_energy(ol_sim *s, double *out) {
+  if (!s->have_state) return fail(s, -5, "not initialised");
+  int Q = s->Q, D = s->D, ddf = is_ddf(s);
+  int64_t n = s->n;
+  double *f = (double *)malloc(n * Q * sizeof(double));
+  double *g = ddf ? (double *)malloc(n * Q * sizeof(double)) : NULL;
+  sync_state(s, f, g);
+  double K = 0.0;
+  for (int64_t c = 0; c < n; ++c) {
+    if (s->flag[c] & OL_F_FINE_GHOST) continue;
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q; ++i) {
+      rho += f[c * Q + i];
+      for (int d = 0; d < D; ++d) j[d] += f[c * Q + i] * s->c[i][d];
+    }
+    double j2 = 0.0;
+    for (int d = 0; d < D; ++d) j2 += j[d] * j[d];
+    K += ldexp(1.0, -D * s->lev[c]) * 0.5 * j2 / rho;
+  }
+  *out = K;
+  free(f);
+  free(g);
+  return 0;
+}
+
 int ol_counters(const ol_sim *s, int64_t *upd, int64_t *nit, int64_t *ncalls) {
   if (upd)
     for (int l = 0; l < s->L; ++l) upd[l] = s->upd[l];

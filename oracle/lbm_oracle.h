@@ -69,6 +69,8 @@ int ol_init(ol_sim *s, const double *moments);
 int ol_step(ol_sim *s, int64_t n_coarse_steps);
 int ol_moments(ol_sim *s, double *out);
 int ol_sums(ol_sim *s, double *out); /* mass, momentum[D], energy (DDF) */
+/* sum of 2^(-D l) rho |u|^2 / 2 over the cells that are not fine ghosts */
+int ol_kinetic_energy(ol_sim *s, double *out);
 int ol_set_face(ol_sim *s, int face, const ol_face *f);
 int ol_counters(const ol_sim *s, int64_t *updates_per_level,
                 int64_t *newton_iters, int64_t *newton_calls);

@@ -71,6 +71,7 @@ def lib():
         L.ol_step.argtypes = [vp, i64]
         L.ol_moments.argtypes = [vp, C.c_void_p]
         L.ol_sums.argtypes = [vp, C.c_void_p]
+        L.ol_kinetic_energy.argtypes = [vp, C.c_void_p]
         L.ol_set_face.argtypes = [vp, C.c_int, C.POINTER(Face)]
         L.ol_counters.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_void_p]
         L.ol_get_state.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -224,6 +225,11 @@ class Oracle:
         out = np.zeros(2 + self.D)
         self._check(self._L.ol_sums(self.h, _ptr(out)))
         return out
+
+    def kinetic_energy(self):
+        out = C.c_double()
+        self._check(self._L.ol_kinetic_energy(self.h, C.byref(out)))
+        return out.value
 
     def counters(self):
         upd = np.zeros(8, np.int64)

@@ -153,3 +153,96 @@ def test_uniform_flow_through_equilibrium_and_neumann_faces(lattice, collision):
     ref = [rho0, u0[0], u0[1]] + ([T] if ddf else [])
     for k, v in enumerate(ref):
         assert np.max(np.abs(m[k] - v)) < 1e-12, (k, np.max(np.abs(m[k] - v)))
+
+
+def _walk_source(x, faces_in, E, B):
+    """first fluid cell along the inward normal of every open face whose
+    B-cell layer holds x: step inward one cell at a time until the cell
+    leaves that face's layer (corners move along both normals)"""
+    q = list(x)
+    for fc in faces_in:
+        a, hi = fc // 2, fc & 1
+        while (q[a] >= E[a] - B) if hi else (q[a] < B):
+            q[a] += -1 if hi else 1
+    return tuple(q)
+
+
+@pytest.mark.parametrize("lattice,collision", [("D2Q9", "BGK"), ("D2Q21", "RR"), ("D2Q37", "DDF_POLY")])
+def test_neumann_one_step_non_uniform_closed_form(lattice, collision):
+    """Neumann faces on all four sides of a non-uniform field (App. A.3):
+    after one step every population equals the post-collision population of
+    its pull source, where a boundary cell's post-collision populations are
+    those of the first fluid cell along the inward normal (both normals at a
+    corner).  The state is at equilibrium, so a collision leaves it
+    unchanged and f* = f_eq at each cell's own moments.  The sources and the
+    streaming are recomputed here from coordinates alone (no exported
+    neighbour or source list); a source one cell off, or a corner that is
+    not clamped along both normals, changes the boundary values."""
+    nx, ny = 14, 12
+    ddf = collision.startswith("DDF")
+    w = channel(lattice, collision, nx, ny, [W.Face("neumann"), W.Face("neumann"),
+                                              W.Face("neumann"), W.Face("neumann")])
+    r = np.random.default_rng(11)
+
+    def init(coords, level):
+        x = coords[:, 0] + 0.5
+        y = coords[:, 1] + 0.5
+        n = len(coords)
+        rho = 1.0 + 0.08 * np.sin(2 * np.pi * x / nx) * np.cos(2 * np.pi * y / ny) + 0.02 * r.random(n)
+        m = [rho, 0.03 * np.cos(2 * np.pi * y / ny) + 0.01 * r.random(n), 0.02 * np.sin(2 * np.pi * x / nx)]
+        if ddf:
+            m.append(1.0 + 0.05 * r.random(n))
+        return np.vstack(m)
+
+    w.init = init
+    o = Oracle.from_workload(w)
+    e = o.export()
+    coords = e["coords"][:, :2]
+    m0 = init(coords, e["level"])
+    o.init(m0)
+    B, Q = o.B, o.Q
+    index = {tuple(int(v) for v in coords[c]): c for c in range(o.n)}
+    # post-collision state: the equilibrium of every cell's own moments
+    Pf = np.zeros((o.n, Q))
+    Pg = np.zeros((o.n, Q)) if ddf else None
+    for c in range(o.n):
+        fe, ge, _ = o.feq(m0[0, c], m0[1:3, c], m0[3, c] if ddf else 0.0)
+        Pf[c] = fe
+        if ddf:
+            Pg[c] = ge
+    E = (nx, ny)
+    src = np.arange(o.n)
+    for c in range(o.n):
+        x = tuple(int(v) for v in coords[c])
+        faces_in = [fc for fc in range(4) if ((x[fc // 2] >= E[fc // 2] - B) if fc & 1 else (x[fc // 2] < B))]
+        if faces_in:
+            q = _walk_source(x, faces_in, E, B)
+            src[c] = index[q]
+            assert e["flags"][c] & F_BC_NEUMANN
+        else:
+            assert not e["flags"][c] & (F_BC_NEUMANN | F_BC_EQ)
+    Pf = Pf[src]
+    if ddf:
+        Pg = Pg[src]
+    # pull streaming by coordinates; a source outside an open face keeps
+    # the cell's own post-collision population
+    f_exp = np.empty_like(Pf)
+    g_exp = np.empty_like(Pf) if ddf else None
+    for c in range(o.n):
+        x = coords[c]
+        for i in range(Q):
+            q = (int(x[0]) - int(o.c[i][0]), int(x[1]) - int(o.c[i][1]))
+            s = index.get(q, c)
+            f_exp[c, i] = Pf[s, i]
+            if ddf:
+                g_exp[c, i] = Pg[s, i]
+    o.step(1)
+    f, g, _ = o.state()
+    assert np.max(np.abs(f - f_exp)) < 1e-14 * np.max(np.abs(f_exp))
+    if ddf:
+        assert np.max(np.abs(g - g_exp)) < 1e-14 * np.max(np.abs(g_exp))
+    # the case discriminates: a boundary cell's copied state differs from
+    # the equilibrium of its own moments
+    bc = np.nonzero(src != np.arange(o.n))[0]
+    feq_own = np.array([o.feq(m0[0, c], m0[1:3, c], m0[3, c] if ddf else 0.0)[0] for c in bc])
+    assert np.min(np.max(np.abs(Pf[bc] - feq_own), axis=1)) > 1e-5

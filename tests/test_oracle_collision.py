@@ -320,3 +320,65 @@ def test_newton_rejects_unrealizable_state():
     o = Oracle("D2Q21", "DDF_NEWTON", T0=0.65, gamma=1.4)
     it, _ = o.newton((2.5, 0.0), 3.0, max_it=60)
     assert it < 0
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q27"])
+def test_rr_trace_equilibration(name):
+    """RR with trace equilibration (App. A.2, closing remark on the bulk
+    relaxation): the trace of the second-order non-equilibrium tensor is
+    relaxed with a relaxation time of one (it vanishes after collision) while
+    its deviatoric part keeps the factor (1 - 1/tau); mass and momentum are
+    conserved, and the kept third- and higher-order non-equilibrium moments
+    follow from the filtered second-order tensor (pair-sum closed form).
+    Every reference quantity is computed here from raw moments of the
+    populations (second moment minus rho u u minus rho cs2 I), a route the
+    oracle does not take (it projects f - f_eq on the Hermite basis).  A
+    wrong sign or a wrong 1/D in the trace removal leaves a non-zero trace
+    and fails."""
+    o = Oracle(name, "RR", nu_finest=0.1, trace_eq=True)
+    o_plain = Oracle(name, "RR", nu_finest=0.1)
+    D = o.D
+    xi = o.c[:, :D].astype(float)
+    cs2 = o.cs2
+    for tau in (0.62, 0.9, 1.7):
+        k = 1.0 - 1.0 / tau
+        for _ in range(4):
+            rho = 0.9 + 0.2 * rng.random()
+            u = 0.15 * (rng.random(D) - 0.5)
+            fe, _, _ = o.feq(rho, u)
+            # a bulk-heavy perturbation: isotropic plus random parts
+            f = fe * (1.0 + 0.04 * (rng.random(o.Q) - 0.5) + 0.03 * ((xi ** 2).sum(1) - D * cs2))
+            fs, _, _, _ = o.collide(tau, f)
+            rho0 = f.sum()
+            u0 = xi.T @ f / rho0
+            assert abs(fs.sum() - rho0) < 1e-14
+            assert np.max(np.abs(xi.T @ fs - rho0 * u0)) < 1e-15
+            P = np.einsum("i,ia,ib->ab", f, xi, xi)
+            aneq = P - rho0 * np.outer(u0, u0) - rho0 * cs2 * np.eye(D)
+            assert abs(np.trace(aneq)) > 1e-4  # the case has a bulk part to remove
+            dev = aneq - np.trace(aneq) / D * np.eye(D)
+            Ps = np.einsum("i,ia,ib->ab", fs, xi, xi)
+            aneq_s = Ps - rho0 * np.outer(u0, u0) - rho0 * cs2 * np.eye(D)
+            assert abs(np.trace(aneq_s)) < 1e-14, np.trace(aneq_s)
+            assert np.max(np.abs(aneq_s - k * dev)) < 1e-14
+            # kept higher orders: the pair-sum closed form on the filtered tensor
+            for m in itertools.product(range(3), repeat=D):
+                tup = [d for d in range(D) for _ in range(m[d])]
+                n = len(tup)
+                if n < 3:
+                    continue
+                an = 0.0
+                for p, q in itertools.combinations(range(n), 2):
+                    pu = 1.0
+                    for kk in range(n):
+                        if kk not in (p, q):
+                            pu *= u0[tup[kk]]
+                    an += dev[tup[p], tup[q]] * pu
+                aeq = rho0 * np.prod(u0 ** np.array(m))
+                got = hermite_project(o, fs, m)
+                assert abs(got - (aeq + k * an)) < 3e-15, (m, got, aeq + k * an)
+            # without the flag the trace keeps the factor (1 - 1/tau)
+            fp, _, _, _ = o_plain.collide(tau, f)
+            Pp = np.einsum("i,ia,ib->ab", fp, xi, xi)
+            tr_p = np.trace(Pp - rho0 * np.outer(u0, u0) - rho0 * cs2 * np.eye(D))
+            assert abs(tr_p - k * np.trace(aneq)) < 1e-14

@@ -318,3 +318,38 @@ def test_sod_numerical_equilibrium_against_exact_riemann(lattice, theta):
     assert e256 < 4e-3, e256
     assert e512 < 0.75 * e256, (e256, e512)
     assert np.nanmin(m[0]) > 0.12 and np.nanmax(m[0]) < 1.001
+
+
+def test_kinetic_energy_monitor():
+    """The kinetic-energy reduction (the convergence monitor of Sec. 5.2): a
+    uniform flow carries rho |u|^2 / 2 times the domain area (closed form,
+    refined band included, fine ghosts excluded), and a decaying shear wave
+    u_x = U sin(k y) loses it as exp(-2 nu k^2 t) (twice the amplitude rate,
+    to the scheme's second-order error).  The density is uniform to O(U^2),
+    so the energy of the wave is rho U^2 / 4 times the area."""
+    n = 32
+    w = W.shear(n=n, levels=2, kind="random", u0=0.0, band=[(0.25, 0.75)])
+    rho0, u0 = 1.1, (0.04, -0.03)
+    w.init = lambda coords, level: np.vstack([np.full(len(coords), rho0), np.full(len(coords), u0[0]),
+                                              np.full(len(coords), u0[1])])
+    o = Oracle.from_workload(w)
+    o.init_workload(w)
+    ke = o.kinetic_energy()
+    assert abs(ke - 0.5 * rho0 * (u0[0] ** 2 + u0[1] ** 2) * n * n) < 1e-14 * n * n
+    o.step(3)
+    assert abs(o.kinetic_energy() - ke) < 1e-13 * ke
+    n, U = 64, 1e-3
+    w = W.shear(n=n, levels=1, kind="wave", u0=U, nu_finest=0.05)
+    o = Oracle.from_workload(w)
+    o.init_workload(w)
+    k0 = o.kinetic_energy()
+    assert abs(k0 - 0.25 * U * U * n * n) < 1e-3 * k0
+    t1, t2 = n, 5 * n
+    o.step(t1)
+    k1 = o.kinetic_energy()
+    o.step(t2 - t1)
+    k2 = o.kinetic_energy()
+    nu = o.cs2 * (o.tau(0) - 0.5)
+    kk = 2 * math.pi / n
+    rate = -math.log(k2 / k1) / (t2 - t1) / (2 * nu * kk * kk)
+    assert abs(rate - 1.0) < 1e-3, rate

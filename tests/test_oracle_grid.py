@@ -46,6 +46,15 @@ def tiny_cases():
     w.refine = [W.Mask(m, (0, 0))]
     w.faces = [W.Face("wall"), W.Face("wall"), W.Face("periodic"), W.Face("periodic"), W.Face(), W.Face()]
     cases.append(("blob", w))
+    # three-cell-deep boundary layers (D2Q21 reaches three cells): an
+    # equilibrium inflow with top / bottom equilibrium faces and a Neumann
+    # outflow meeting them at the corners, around a refined box
+    w = W.shear(n=24, levels=2, lattice="D2Q21", collision="RR", steps=1)
+    w.ext = (24, 20)
+    w.refine = [W._box_mask(w.ext, 2, 0, (8, 6), (16, 14))]
+    w.faces = [W.Face("equilibrium", u=(0.1, 0, 0), T=1.0), W.Face("neumann"),
+               W.Face("equilibrium", u=(0.1, 0, 0), T=1.0), W.Face("neumann"), W.Face(), W.Face()]
+    cases.append(("corners", w))
     return cases
 
 
@@ -129,6 +138,30 @@ def test_grid_brute_force(name, w):
                 assert got in (NONE, SOLID)
                 if got == SOLID:
                     assert w.solid[l] is not None and w.solid[l].dense(E[l])[tuple(reversed(src))] == 1
+    # boundary layers (App. A.3): a cell within B cells of a Neumann or
+    # equilibrium face is a boundary cell; its source is found by walking
+    # inward along the normal of each such face until the walk leaves that
+    # face's layer (corners along both normals); equilibrium faces win over
+    # Neumann ones for the flag
+    bc_src = e["bc_src"]
+    B = o.B
+    for c in range(n):
+        l = int(level[c])
+        x = [int(v) for v in coords[c][:D]]
+        faces_in = [fc for fc in range(2 * D) if w.faces[fc].kind in ("neumann", "equilibrium")
+                    and ((x[fc // 2] >= E[l][fc // 2] - B) if fc & 1 else (x[fc // 2] < B))]
+        if not faces_in:
+            assert bc_src[c] == -1 and not flags[c] & (F_BC_NEUMANN | F_BC_EQ)
+            continue
+        q = list(x)
+        for fc in faces_in:
+            a = fc // 2
+            step = -1 if fc & 1 else 1
+            while (q[a] >= E[l][a] - B) if fc & 1 else (q[a] < B):
+                q[a] += step
+        assert bc_src[c] == index[(l,) + tuple(q)], (c, x, q)
+        kinds = {w.faces[fc].kind for fc in faces_in}
+        assert flags[c] & (F_BC_EQ if "equilibrium" in kinds else F_BC_NEUMANN)
     # bulk cells pull every population from a cell; neighbour links are
     # mutual between cells whose populations stream both ways
     for c in range(n):
