@@ -223,14 +223,23 @@ typedef struct {
   double mass, momentum[3], energy; /* sum over non-fine-ghost cells of
                                        2^(-D l) sum_i (1, xi, |xi|^2/2) f_i
                                        (+ g/2 for DDF), FP64              */
+  double kinetic_energy;            /* sum over the same cells of
+                                       2^(-D l) rho |u|^2 / 2 (the monitor
+                                       of the convergence test, Sec. 5.2) */
   int64_t updates[8];               /* cell updates per level             */
   int64_t newton_calls, newton_iterations, newton_failures;
   int64_t mlp_fallbacks, nonfinite_cells;
   int64_t coarse_steps;
+  int64_t newton_hist[16];          /* Newton solves of the collisions by
+                                       steps taken: bin k < 15 counts solves
+                                       of k steps, bin 15 longer ones and
+                                       failures (per-cell iteration counts
+                                       as a stability monitor, Sec. 4.4)  */
 } lbm_stats;
 
 /* Conservation sums and counters; synchronous. */
 lbm_status lbm_stats_get(lbm_ctx *ctx, lbm_stats *out);
+
 
 /* Wait for all enqueued work; reports a latched numeric failure. */
 lbm_status lbm_sync(lbm_ctx *ctx);

@@ -14,7 +14,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "liblbm.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HIP_SOURCES = ["k_d2q9.hip", "k_d3q27.hip", "k_d2q13.hip", "k_d2q21.hip", "k_d2q37.hip", "mlp.hip", "k_remesh.hip"]
+HIP_SOURCES = ["k_d2q9.hip", "k_d3q27.hip", "k_d2q13.hip", "k_d2q21.hip", "k_d2q37.hip", "k_d2q37_newton64.hip",
+               "k_d2q37_newton32.hip", "mlp.hip", "k_remesh.hip", "sums.hip"]
 CXX_SOURCES = ["grid_builder.cpp", "layout.cpp", "remesh.cpp", "lbm_api.cpp"]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -38,17 +39,31 @@ def torch_lib_dir() -> str:
     return os.path.join(os.path.dirname(torch.__file__), "lib")
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
+def _stale(obj: str, src: str) -> bool:
+    """an object is stale when it is older than its source or any header"""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [src] + [os.path.join(d, h) for d in (CSRC, os.path.join(ROOT, "include"))
+                    for h in os.listdir(d) if h.endswith((".h", ".cuh"))]
+    return any(os.path.getmtime(p) > t for p in deps)
+
+
+def build(verbose: bool = False, jobs: int = 8, incremental: bool = False) -> str:
+    """compile every source (or, with incremental=True, only the objects
+    older than their source or a header) and link liblbm.so"""
     os.makedirs(BUILD, exist_ok=True)
     cmds = []
     objs = []
     for s in HIP_SOURCES:
         o = os.path.join(BUILD, s.replace(".hip", ".o"))
-        cmds.append([os.path.join(ROCM, "bin", "hipcc")] + HIPCC_FLAGS + ["-c", os.path.join(CSRC, s), "-o", o])
+        if not incremental or _stale(o, os.path.join(CSRC, s)):
+            cmds.append([os.path.join(ROCM, "bin", "hipcc")] + HIPCC_FLAGS + ["-c", os.path.join(CSRC, s), "-o", o])
         objs.append(o)
     for s in CXX_SOURCES:
         o = os.path.join(BUILD, s.replace(".cpp", ".o"))
-        cmds.append(["g++"] + CXX_FLAGS + ["-c", os.path.join(CSRC, s), "-o", o])
+        if not incremental or _stale(o, os.path.join(CSRC, s)):
+            cmds.append(["g++"] + CXX_FLAGS + ["-c", os.path.join(CSRC, s), "-o", o])
         objs.append(o)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         for out in ex.map(_run, cmds):
@@ -63,4 +78,4 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="-i" in sys.argv))

@@ -89,6 +89,7 @@ __global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
       }
       if (it < 0) count_add(a.counters, CNT_NEWTON_FAIL, 1);
       else count_add(a.counters, CNT_NEWTON_ITERS, (unsigned long long)it);
+      count_hist(a.counters, it);
     } else {
       // the network's multipliers as they are
       double G[NLAM];

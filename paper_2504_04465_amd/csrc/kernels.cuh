@@ -66,6 +66,21 @@ struct Sto<__half> {
   }
 };
 
+// Newton multipliers (warm start of the numerical equilibrium) are kept in
+// FP64 next to FP64 populations, so that an FP64 run restarts every solve
+// from the multipliers it converged to; reduced-precision storage keeps them
+// in FP32.
+template <class S>
+struct LamOf {
+  using T = float;
+};
+template <>
+struct LamOf<double> {
+  using T = double;
+};
+template <class S>
+using LamT = typename LamOf<S>::T;
+
 // Blocks are dealt to the 8 XCDs round-robin; remap so that each XCD works
 // on one contiguous range of Z-ordered cells and its L2 sees the neighbours.
 __device__ inline int64_t xcd_block() {
@@ -951,6 +966,23 @@ __device__ inline void count_add(unsigned long long *ctr, int which, unsigned lo
   if (v) atomicAdd(ctr + CNT_COUNT * (blockIdx.x & (CNT_COPIES - 1u)) + which, v);
 }
 
+// Histogram of the Newton steps per solve (the per-cell iteration counts
+// the paper keeps to monitor stability, Sec. 4.4): bin k < NHIST - 1 counts
+// solves of k steps, the last bin longer solves and failures (it < 0).  The
+// active lanes of a wavefront add one atomic per distinct bin.
+__device__ inline void count_hist(unsigned long long *ctr, int it) {
+  const int bin = (it < 0 || it >= NHIST - 1) ? NHIST - 1 : it;
+  unsigned long long *base = ctr + CNT_COUNT * (blockIdx.x & (CNT_COPIES - 1u)) + CNT_HIST0;
+  uint64_t todo = __ballot(1);
+  while (todo) {
+    const int lead = __ffsll((unsigned long long)todo) - 1;
+    const int b = __shfl(bin, lead);
+    const uint64_t same = __ballot(bin == b) & todo;
+    if ((int)(threadIdx.x & 63) == lead) atomicAdd(base + b, (unsigned long long)__popcll(same));
+    todo &= ~same;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // collide and stream (pull) for the cells [begin, begin + count) of a level
 // ---------------------------------------------------------------------------
@@ -1045,7 +1077,7 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
       double lam[NLAM];
       if constexpr (COLL >= COLL_DDF_NEWTON) {
 #pragma unroll
-        for (int k = 0; k < NLAM; ++k) lam[k] = (double)a.lam[(int64_t)k * stride + c];
+        for (int k = 0; k < NLAM; ++k) lam[k] = (double)((const LamT<S> *)a.lam)[(int64_t)k * stride + c];
       }
       int it;
       if constexpr (COLL >= COLL_DDF_NEWTON) {
@@ -1073,8 +1105,9 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
         count_add(a.counters, CNT_NEWTON_CALLS, 1);
         if (it < 0) count_add(a.counters, CNT_NEWTON_FAIL, 1);
         else count_add(a.counters, CNT_NEWTON_ITERS, (unsigned long long)it);
+        count_hist(a.counters, it);
 #pragma unroll
-        for (int k = 0; k < NLAM; ++k) a.lam[(int64_t)k * stride + c] = (float)lam[k];
+        for (int k = 0; k < NLAM; ++k) ((LamT<S> *)a.lam)[(int64_t)k * stride + c] = (LamT<S>)lam[k];
       }
       C te = (C)a.ph.tau;
       if (a.ph.sensor_on) te *= sensor_alpha<L, C>(f, feq, te, (C)a.ph.sensor_A);
@@ -1183,9 +1216,9 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
     const int64_t G = valid && mine ? a.ghost_cell[gk] : 0;
 #pragma unroll
     for (int k = 0; k < NLAM; ++k) {
-      double v = ch >= 0 && mine ? (double)a.lam[(int64_t)k * a.stride + ch] : 0.0;
+      double v = ch >= 0 && mine ? (double)((const LamT<S> *)a.lam)[(int64_t)k * a.stride + ch] : 0.0;
       v = group_sum<NCH, double>(v);
-      if (lead && mine) a.lam[(int64_t)k * a.stride + G] = (float)(v / (double)nf);
+      if (lead && mine) ((LamT<S> *)a.lam)[(int64_t)k * a.stride + G] = (LamT<S>)(v / (double)nf);
     }
   }
 }
@@ -1217,7 +1250,7 @@ __global__ void __launch_bounds__(BLOCK) k_explode(const EArgs a) {
     for (int i = 0; i < L::Q; ++i) ((S *)a.gout_fine)[(int64_t)i * a.stride + ch] = vg[i];
   if (LAM)
 #pragma unroll
-    for (int k = 0; k < NLAM; ++k) a.lam[(int64_t)k * a.stride + ch] = a.lam[(int64_t)k * a.stride + G];
+    for (int k = 0; k < NLAM; ++k) ((LamT<S> *)a.lam)[(int64_t)k * a.stride + ch] = ((LamT<S> *)a.lam)[(int64_t)k * a.stride + G];
 }
 
 // ---------------------------------------------------------------------------
@@ -1268,7 +1301,7 @@ __global__ void __launch_bounds__(BLOCK) k_bcfill(const BArgs a) {
       for (int i = 0; i < L::Q; ++i) g[(int64_t)i * a.stride + c] = vg[i];
     if (LAM)
 #pragma unroll
-      for (int q = 0; q < NLAM; ++q) a.lam[(int64_t)q * a.stride + c] = a.lam[(int64_t)q * a.stride + src];
+      for (int q = 0; q < NLAM; ++q) ((LamT<S> *)a.lam)[(int64_t)q * a.stride + c] = ((LamT<S> *)a.lam)[(int64_t)q * a.stride + src];
     return;
   }
   C rho = (C)frho;
@@ -1282,12 +1315,12 @@ __global__ void __launch_bounds__(BLOCK) k_bcfill(const BArgs a) {
   double lam[NLAM];
   if (LAM)
 #pragma unroll
-    for (int q = 0; q < NLAM; ++q) lam[q] = (double)a.lam[(int64_t)q * a.stride + c];
+    for (int q = 0; q < NLAM; ++q) lam[q] = (double)((const LamT<S> *)a.lam)[(int64_t)q * a.stride + c];
   const int it = equilibrium_any<L, COLL, C>(rho, u, (C)fT, a.ph, lam, a.ph.warm != 0, feq, geq);
   if (LAM) {
     if (it < 0) count_add(a.counters, CNT_NEWTON_FAIL, 1);
 #pragma unroll
-    for (int q = 0; q < NLAM; ++q) a.lam[(int64_t)q * a.stride + c] = (float)lam[q];
+    for (int q = 0; q < NLAM; ++q) ((LamT<S> *)a.lam)[(int64_t)q * a.stride + c] = (LamT<S>)lam[q];
   }
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
@@ -1322,7 +1355,7 @@ __global__ void __launch_bounds__(BLOCK) k_gather(const MArgs a) {
       if (DDF) a.out[(int64_t)(Q + i) * a.n + k] = (double)g[i];
     }
     if (a.lam_out)
-      for (int q = 0; q < NLAM; ++q) a.lam_out[(int64_t)q * a.n + k] = (double)a.lam[(int64_t)q * a.stride + c];
+      for (int q = 0; q < NLAM; ++q) a.lam_out[(int64_t)q * a.n + k] = (double)((const LamT<S> *)a.lam)[(int64_t)q * a.stride + c];
     return;
   }
   const bool live = t < a.count;  // whole wavefronts
@@ -1359,27 +1392,59 @@ __global__ void __launch_bounds__(BLOCK) k_gather(const MArgs a) {
     }
     if (a.lam_out)
       for (int k = 0; k < NLAM; ++k)
-        a.lam_out[(int64_t)k * a.n + cell] = (double)a.lam[(int64_t)k * a.stride + c];
+        a.lam_out[(int64_t)k * a.n + cell] = (double)((const LamT<S> *)a.lam)[(int64_t)k * a.stride + c];
     return;
   }
-  // mode 2: volume-weighted conserved sums, deterministic block reduction
-  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (valid && !fine_ghost) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const double fi = (double)f[i];
-      s[0] += fi;
-#pragma unroll
-      for (int d = 0; d < L::D; ++d) s[1 + d] += fi * cx_<L>(i, d);
-      const int n2 = cx_<L>(i, 0) * cx_<L>(i, 0) + cx_<L>(i, 1) * cx_<L>(i, 1) + cx_<L>(i, 2) * cx_<L>(i, 2);
-      s[4] += 0.5 * (n2 * fi + (DDF ? (double)g[i] : 0.0));
-    }
-#pragma unroll
-    for (int k = 0; k < 5; ++k) s[k] *= a.vol;
-  }
+}
+
+// ---------------------------------------------------------------------------
+// conserved sums at the synchronisation point (Sec. 4.1's reductions): mass,
+// momentum, total energy (|xi|^2 f / 2 + g / 2) and kinetic energy
+// (rho |u|^2 / 2) of the cells that are not fine ghosts, volume-weighted,
+// in FP64.  Each block strides over the level's 256-slot tiles (tile b,
+// b + gridDim.x, ...) and writes one partial per quantity, so the partials
+// take gridDim.x x 6 doubles whatever the size of the level; every thread
+// accumulates its tiles in a fixed order and the block reduction has a fixed
+// shape, so the result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+template <class L, class S, bool PRE, bool DDF, int AA = 0>
+__global__ void __launch_bounds__(BLOCK) k_sums(const MArgs a) {
+  using C = typename Sto<S>::C;
+  constexpr int Q = L::Q;
+  __shared__ uint32_t nbs[BLOCK / 64][Brick<L>::NBP];
   __shared__ double red[BLOCK / 64][6];
+  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const int64_t tiles = (a.count + BLOCK - 1) / BLOCK;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t t = tile * BLOCK + threadIdx.x;
+    const bool live = t < a.count;  // whole wavefronts
+    const int64_t c = a.begin + (live ? t : 0);
+    const int32_t brick = stage_bricks<L, S>(a.topo, nbs, c, live);
+    const int32_t cell = live ? a.cell_of[c] : -1;
+    if (cell >= 0 && !(a.flags[c] & F_FINE_GHOST)) {
+      C f[Q];
+      C g[DDF ? Q : 1];
+      gather<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[threadIdx.x >> 6], a.stride,
+                                 a.vbase, c, threadIdx.x & 63, brick, a.topo.xmask[brick], a.uw, a.cs2w, f, g);
+      double q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
+      for (int i = 0; i < Q; ++i) {
+        const double fi = (double)f[i];
+        q[0] += fi;
+#pragma unroll
+        for (int d = 0; d < L::D; ++d) q[1 + d] += fi * cx_<L>(i, d);
+        const int n2 = cx_<L>(i, 0) * cx_<L>(i, 0) + cx_<L>(i, 1) * cx_<L>(i, 1) + cx_<L>(i, 2) * cx_<L>(i, 2);
+        q[4] += 0.5 * (n2 * fi + (DDF ? (double)g[i] : 0.0));
+      }
+      // kinetic energy rho |u|^2 / 2 = |j|^2 / (2 rho) of the cell
+      q[5] = 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) s[k] += q[k] * a.vol;
+    }
+    __syncthreads();  // the next tile restages the brick table
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
     double v = s[k];
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
@@ -1388,10 +1453,10 @@ __global__ void __launch_bounds__(BLOCK) k_gather(const MArgs a) {
   const int wid = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0)
 #pragma unroll
-    for (int k = 0; k < 5; ++k) red[wid][k] = s[k];
+    for (int k = 0; k < 6; ++k) red[wid][k] = s[k];
   __syncthreads();
   if (threadIdx.x == 0)
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 6; ++k) {
       double v = 0.0;
       for (int w = 0; w < BLOCK / 64; ++w) v += red[w][k];
       a.partials[(int64_t)blockIdx.x * 6 + k] = v;
@@ -1418,7 +1483,7 @@ __global__ void __launch_bounds__(BLOCK) k_init(const IArgs a) {
       if (DDF) Sto<S>::st(g, (int64_t)i * a.stride + c, (C)a.src_g[(int64_t)i * a.n + k0], 0.0);
     }
     if (LAM && a.src_lam)
-      for (int k = 0; k < NLAM; ++k) a.lam[(int64_t)k * a.stride + c] = (float)a.src_lam[(int64_t)k * a.n + k0];
+      for (int k = 0; k < NLAM; ++k) ((LamT<S> *)a.lam)[(int64_t)k * a.stride + c] = (LamT<S>)a.src_lam[(int64_t)k * a.n + k0];
     return;
   }
   const C rho = (C)a.src[k0];
@@ -1430,7 +1495,7 @@ __global__ void __launch_bounds__(BLOCK) k_init(const IArgs a) {
   const int it = equilibrium_any<L, COLL, C>(rho, u, T, a.ph, lam, false, feq, geq);
   if (LAM) {
     if (it < 0) count_add(a.counters, CNT_NEWTON_FAIL, 1);
-    for (int k = 0; k < NLAM; ++k) a.lam[(int64_t)k * a.stride + c] = (float)lam[k];
+    for (int k = 0; k < NLAM; ++k) ((LamT<S> *)a.lam)[(int64_t)k * a.stride + c] = (LamT<S>)lam[k];
   }
   if (!(rho > (C)0) || !isfinite(rho)) count_add(a.counters, CNT_NONFINITE, 1);
 #pragma unroll
@@ -1471,7 +1536,7 @@ __global__ void __launch_bounds__(BLOCK) k_sensor(const MArgs a, const PhysArgs 
   cell_moments<L, C, DDF>(f, g, (C)a.Cv, rho, u, T);
   double lam[NLAM];
 #pragma unroll
-  for (int k = 0; k < NLAM; ++k) lam[k] = COLL >= COLL_DDF_NEWTON ? (double)a.lam[(int64_t)k * a.stride + c] : 0.0;
+  for (int k = 0; k < NLAM; ++k) lam[k] = COLL >= COLL_DDF_NEWTON ? (double)((const LamT<S> *)a.lam)[(int64_t)k * a.stride + c] : 0.0;
   C feq[Q], geq[Q];
   equilibrium_any<L, COLL, C>(rho, u, T, ph, lam, true, feq, geq);
   constexpr C tiny = sizeof(C) == 8 ? (C)1e-300 : (C)1e-30;
@@ -1524,6 +1589,13 @@ struct Launch {
     else if (pre) hipLaunchKernelGGL((k_gather<L, S, true, DDF>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
     else hipLaunchKernelGGL((k_gather<L, S, false, DDF>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
   }
+  static void sums(const MArgs &a, bool pre, hipStream_t s) {
+    if (a.count <= 0) return;
+    const dim3 nb((unsigned)sum_blocks(a.count));
+    if (a.aa == 2) hipLaunchKernelGGL((k_sums<L, S, false, DDF, 2>), nb, dim3(BLOCK), 0, s, a);
+    else if (pre) hipLaunchKernelGGL((k_sums<L, S, true, DDF>), nb, dim3(BLOCK), 0, s, a);
+    else hipLaunchKernelGGL((k_sums<L, S, false, DDF>), nb, dim3(BLOCK), 0, s, a);
+  }
   static void init(const IArgs &a, hipStream_t s) {
     if (a.n <= 0) return;
     hipLaunchKernelGGL((k_init<L, COLL, S>), dim3(nblocks(a.n)), dim3(BLOCK), 0, s, a);
@@ -1543,6 +1615,7 @@ struct Launch {
     o.explode = &explode;
     o.bcfill = &bcfill;
     o.gather = &gather;
+    o.sums = &sums;
     o.init = &init;
     o.sizeof_storage = (int)sizeof(S);
     return o;

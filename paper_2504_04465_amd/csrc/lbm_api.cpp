@@ -55,7 +55,8 @@ struct lbm_ctx {
   int32_t *d_cell_of = nullptr, *d_slot_of = nullptr, *d_crow = nullptr;
   uint8_t *d_flags = nullptr;
   double *d_sigma = nullptr, *d_rhoinf = nullptr;
-  float *d_lam = nullptr;
+  void *d_lam = nullptr;   // multipliers: FP64 with FP64 storage, else FP32
+  int lam_bytes = 4;
   int32_t *d_ghost = nullptr, *d_child = nullptr;
   uint64_t *d_unknown = nullptr;
   int32_t *d_bc_cell = nullptr, *d_bc_src = nullptr;
@@ -159,6 +160,24 @@ void dev_release(lbm_ctx *c, void *p) {
   if (c->dfree) c->dfree(p, c->actx);
   else hipFree(p);
 }
+
+// Device buffers of one call: every buffer taken through take() is released
+// when the call returns, on its error paths as on success.
+struct CallBuffers {
+  lbm_ctx *c;
+  std::vector<void *> held;
+  explicit CallBuffers(lbm_ctx *ctx) : c(ctx) {}
+  CallBuffers(const CallBuffers &) = delete;
+  CallBuffers &operator=(const CallBuffers &) = delete;
+  void *take(size_t bytes) {
+    void *p = dev_alloc(c, bytes);
+    if (p) held.push_back(p);
+    return p;
+  }
+  ~CallBuffers() {
+    for (void *p : held) dev_release(c, p);
+  }
+};
 
 template <class T>
 lbm_status upload(lbm_ctx *c, T **dst, const T *src, size_t count) {
@@ -356,6 +375,10 @@ lbm_status numeric_check(lbm_ctx *c) {
 
 double *scratch(lbm_ctx *c, size_t bytes) {
   if (c->scratch_bytes < bytes) {
+    // the old buffer goes back to the allocator before the larger one is taken
+    dev_release(c, c->d_scratch);
+    c->d_scratch = nullptr;
+    c->scratch_bytes = 0;
     c->d_scratch = (double *)dev_alloc(c, bytes);
     c->scratch_bytes = c->d_scratch ? bytes : 0;
   }
@@ -472,6 +495,7 @@ lbm_status lbm_create(const lbm_params *params, lbm_dev_alloc_fn dev_alloc_fn,
   }
   c->ddf = coll >= LBM_DDF_POLY;
   c->lamf = coll >= LBM_DDF_NEWTON;
+  c->lam_bytes = c->p.storage == LBM_FP64 ? 8 : 4;
   *out = c;
   return LBM_OK;
 }
@@ -547,7 +571,7 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
     // and out (and multipliers), plus the level's share of the flag, brick
     // and exception tables and of the sponge fields
     const int Q = c->lat.Q;
-    const double pops = 2.0 * Q * c->ops.sizeof_storage * (c->ddf ? 2 : 1) + (c->lamf ? 2.0 * NLAM * 4 : 0.0);
+    const double pops = 2.0 * Q * c->ops.sizeof_storage * (c->ddf ? 2 : 1) + (c->lamf ? 2.0 * NLAM * c->lam_bytes : 0.0);
     for (int l = 0; l < n_levels; ++l) {
       const int64_t ncell = c->g.off[l + 1] - c->g.off[l];
       const int64_t nsl = c->lay.soff[l + 1] - c->lay.soff[l];
@@ -622,7 +646,7 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
     if ((s = upload(c, &c->d_rhoinf, ri.data(), ri.size())) != LBM_OK) return s;
   }
   if (c->lamf) {
-    c->d_lam = (float *)dev_alloc(c, sizeof(float) * NLAM * c->stride);
+    c->d_lam = dev_alloc(c, (size_t)c->lam_bytes * NLAM * c->stride);
     if (!c->d_lam) return set_err(c, LBM_E_NOMEM, "multiplier allocation failed");
   }
   {
@@ -860,29 +884,32 @@ lbm_status lbm_remesh(lbm_ctx *c, const lbm_mask *refine, const lbm_mask *solid)
   int64_t *d_off = nullptr;
   int32_t *d_src = nullptr;
   double *d_wt = nullptr;
+  auto release_all = [&]() {
+    release_old();
+    dev_release(c, d_off);
+    dev_release(c, d_src);
+    dev_release(c, d_wt);
+  };
   if ((s = upload(c, &d_off, off.data(), off.size())) != LBM_OK ||
       (s = upload(c, &d_src, src.data(), src.size())) != LBM_OK ||
       (s = upload(c, &d_wt, wt.data(), wt.size())) != LBM_OK) {
-    release_old();
+    release_all();
     return s;
   }
   const int64_t n_new = c->N;
   double *nw = scratch(c, sizeof(double) * (size_t)rows * (size_t)std::max<int64_t>(n_new, 1));
   if (!nw) {
-    release_old();
+    release_all();
     return set_err(c, LBM_E_NOMEM, "scratch allocation failed");
   }
   launch_remap(old, n_old, nw, n_new, rows, d_off, d_src, d_wt, c->stream);
   if ((s = check_launch(c)) != LBM_OK) {
-    release_old();
+    release_all();
     return s;
   }
   s = init_common(c, nw, c->ddf ? nw + (size_t)Q * n_new : nullptr,
                   c->lamf ? nw + (size_t)pop_rows * n_new : nullptr, 1, true);
-  release_old();
-  dev_release(c, d_off);
-  dev_release(c, d_src);
-  dev_release(c, d_wt);
+  release_all();
   if (s != LBM_OK) return s;
   c->coarse_steps = steps;
   memcpy(c->updates, upd, sizeof upd);
@@ -1110,35 +1137,42 @@ lbm_status lbm_get_cells(lbm_ctx *c, const int64_t *cells, int64_t n, double *f,
   return LBM_OK;
 }
 
+// The conserved sums of the synchronisation-point state into out[6] (mass,
+// momentum x / y / z, total energy, kinetic energy), enqueued on the
+// context stream: coalescence of every interface, one k_sums launch per
+// level into partials [SUM_LEVELS][SUM_BLOCKS][6], and the fixed-order final
+// reduction.  The caller provides both device buffers.
+static lbm_status enqueue_sums(lbm_ctx *c, double *partials, double *out) {
+  if (c->L > SUM_LEVELS) return set_err(c, LBM_E_ARG, "conserved sums: more than 8 levels");
+  coalesce_all(c);
+  int nb[SUM_LEVELS] = {0};
+  for (int l = 0; l < c->L; ++l) {
+    MArgs a = gather_args(c, l, 2);
+    a.partials = partials + (size_t)l * SUM_BLOCKS * SUM_Q;
+    nb[l] = a.count > 0 ? sum_blocks(a.count) : 0;
+    c->ops.sums(a, read_pre(c, l), c->stream);
+  }
+  launch_sum_partials(partials, nb, c->L, out, c->stream);
+  return check_launch(c);
+}
+
 lbm_status lbm_stats_get(lbm_ctx *c, lbm_stats *out) {
   lbm_status s = need_state(c);
   if (s != LBM_OK) return s;
   if (!out) return set_err(c, LBM_E_ARG, "null output");
   memset(out, 0, sizeof *out);
-  std::vector<int64_t> blocks(c->L), boff(c->L + 1, 0);
-  for (int l = 0; l < c->L; ++l) {
-    blocks[l] = (c->lay.soff[l + 1] - c->lay.soff[l] + 255) / 256;
-    boff[l + 1] = boff[l] + blocks[l];
-  }
-  double *d = scratch(c, sizeof(double) * 6 * std::max<int64_t>(boff[c->L], 1));
+  double *d = scratch(c, sizeof(double) * (SUM_PARTIALS + SUM_Q));
   if (!d) return set_err(c, LBM_E_NOMEM, "scratch allocation failed");
-  coalesce_all(c);
-  for (int l = 0; l < c->L; ++l) {
-    MArgs a = gather_args(c, l, 2);
-    a.partials = d + 6 * boff[l];
-    c->ops.gather(a, read_pre(c, l), c->stream);
-  }
-  if ((s = check_launch(c)) != LBM_OK) return s;
-  std::vector<double> h(6 * std::max<int64_t>(boff[c->L], 1));
-  HIP_TRY(c, hipMemcpyAsync(h.data(), d, sizeof(double) * 6 * boff[c->L], hipMemcpyDeviceToHost, c->stream));
+  if ((s = enqueue_sums(c, d, d + SUM_PARTIALS)) != LBM_OK) return s;
+  double acc[SUM_Q];
+  HIP_TRY(c, hipMemcpyAsync(acc, d + SUM_PARTIALS, sizeof acc, hipMemcpyDeviceToHost, c->stream));
   unsigned long long cnt[CNT_COUNT];
   if ((s = read_counters(c, cnt)) != LBM_OK) return s;
-  double acc[5] = {0, 0, 0, 0, 0};
-  for (int64_t b = 0; b < boff[c->L]; ++b)
-    for (int k = 0; k < 5; ++k) acc[k] += h[6 * b + k];
   out->mass = acc[0];
   for (int d2 = 0; d2 < 3; ++d2) out->momentum[d2] = acc[1 + d2];
   out->energy = acc[4];
+  out->kinetic_energy = acc[5];
+  for (int k = 0; k < NHIST; ++k) out->newton_hist[k] = (int64_t)cnt[CNT_HIST0 + k];
   for (int l = 0; l < c->L; ++l) out->updates[l] = c->updates[l];
   out->newton_calls = (int64_t)cnt[CNT_NEWTON_CALLS];
   out->newton_iterations = (int64_t)cnt[CNT_NEWTON_ITERS];
@@ -1190,10 +1224,11 @@ lbm_status lbm_mlp_label(lbm_ctx *c, const double *x, int64_t n, double *lambda,
   lbm_status s = mlp_ensure(c);
   if (s != LBM_OK) return s;
   if (n == 0) return LBM_OK;
-  double *dx = (double *)dev_alloc(c, sizeof(double) * 4 * n);
-  double *dl = (double *)dev_alloc(c, sizeof(double) * 8 * n);
-  uint8_t *dok = (uint8_t *)dev_alloc(c, n);
-  int *dit = (int *)dev_alloc(c, sizeof(int) * n);
+  CallBuffers tmp(c);
+  double *dx = (double *)tmp.take(sizeof(double) * 4 * n);
+  double *dl = (double *)tmp.take(sizeof(double) * 8 * n);
+  uint8_t *dok = (uint8_t *)tmp.take(n);
+  int *dit = (int *)tmp.take(sizeof(int) * n);
   if (!dx || !dl || !dok || !dit) return set_err(c, LBM_E_NOMEM, "label allocation failed");
   HIP_TRY(c, hipMemcpyAsync(dx, x, sizeof(double) * 4 * n, hipMemcpyHostToDevice, c->stream));
   mlp_label(dx, n, c->p.newton_tol, c->p.newton_max_it, dl, dok, dit, c->stream);
@@ -1202,10 +1237,6 @@ lbm_status lbm_mlp_label(lbm_ctx *c, const double *x, int64_t n, double *lambda,
   HIP_TRY(c, hipMemcpyAsync(ok, dok, n, hipMemcpyDeviceToHost, c->stream));
   if (iters) HIP_TRY(c, hipMemcpyAsync(iters, dit, sizeof(int) * n, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  dev_release(c, dx);
-  dev_release(c, dl);
-  dev_release(c, dok);
-  dev_release(c, dit);
   return LBM_OK;
 }
 
@@ -1213,8 +1244,9 @@ lbm_status lbm_mlp_predict(lbm_ctx *c, const double *x, int64_t n, double *lambd
   if (!c || !x || !lambda || n < 0) return LBM_E_ARG;
   if (!c->have_mlp) return set_err(c, LBM_E_STATE, "surrogate weights not set");
   if (n == 0) return LBM_OK;
-  double *dx = (double *)dev_alloc(c, sizeof(double) * 4 * n);
-  double *dl = (double *)dev_alloc(c, sizeof(double) * 8 * n);
+  CallBuffers tmp(c);
+  double *dx = (double *)tmp.take(sizeof(double) * 4 * n);
+  double *dl = (double *)tmp.take(sizeof(double) * 8 * n);
   if (!dx || !dl) return set_err(c, LBM_E_NOMEM, "prediction allocation failed");
   HIP_TRY(c, hipMemcpyAsync(dx, x, sizeof(double) * 4 * n, hipMemcpyHostToDevice, c->stream));
   mlp_predict(c->d_mlp_ops, dx, n, dl, c->stream);
@@ -1222,17 +1254,16 @@ lbm_status lbm_mlp_predict(lbm_ctx *c, const double *x, int64_t n, double *lambd
   if (s != LBM_OK) return s;
   HIP_TRY(c, hipMemcpyAsync(lambda, dl, sizeof(double) * 8 * n, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  dev_release(c, dx);
-  dev_release(c, dl);
   return LBM_OK;
 }
 
 lbm_status lbm_mlp_grad(lbm_ctx *c, const float *xh, const float *th, int64_t n, double *loss, float *grad) {
   if (!c || !xh || !th || !grad || n <= 0 || n % 32) return set_err(c, LBM_E_ARG, "bad batch");
   if (!c->have_mlp) return set_err(c, LBM_E_STATE, "surrogate weights not set");
-  float *dx = (float *)dev_alloc(c, sizeof(float) * 4 * n);
-  float *dt = (float *)dev_alloc(c, sizeof(float) * 8 * n);
-  int32_t *dp = (int32_t *)dev_alloc(c, sizeof(int32_t) * n);
+  CallBuffers tmp(c);
+  float *dx = (float *)tmp.take(sizeof(float) * 4 * n);
+  float *dt = (float *)tmp.take(sizeof(float) * 8 * n);
+  int32_t *dp = (int32_t *)tmp.take(sizeof(int32_t) * n);
   if (!dx || !dt || !dp) return set_err(c, LBM_E_NOMEM, "gradient allocation failed");
   std::vector<int32_t> perm(n);
   for (int64_t k = 0; k < n; ++k) perm[k] = (int32_t)k;
@@ -1250,9 +1281,6 @@ lbm_status lbm_mlp_grad(lbm_ctx *c, const float *xh, const float *th, int64_t n,
   HIP_TRY(c, hipMemsetAsync(c->d_mlp_g, 0, sizeof(float) * MLP_PARAMS, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (loss) *loss = lh;
-  dev_release(c, dx);
-  dev_release(c, dt);
-  dev_release(c, dp);
   return LBM_OK;
 }
 
@@ -1313,9 +1341,10 @@ lbm_status lbm_mlp_train(lbm_ctx *c, const double *x, const double *lambda, int6
     xh[4 * i + 3] = (float)((x[4 * i + 3] - 1.75) / 1.25);
     for (int k = 0; k < 8; ++k) th[8 * i + k] = (float)((lambda[8 * i + k] - mu[k]) / sg[k]);
   }
-  float *dx = (float *)dev_alloc(c, sizeof(float) * 4 * n);
-  float *dt = (float *)dev_alloc(c, sizeof(float) * 8 * n);
-  int32_t *dp = (int32_t *)dev_alloc(c, sizeof(int32_t) * n);
+  CallBuffers tmp(c);
+  float *dx = (float *)tmp.take(sizeof(float) * 4 * n);
+  float *dt = (float *)tmp.take(sizeof(float) * 8 * n);
+  int32_t *dp = (int32_t *)tmp.take(sizeof(int32_t) * n);
   if (!dx || !dt || !dp) return set_err(c, LBM_E_NOMEM, "training allocation failed");
   HIP_TRY(c, hipMemcpyAsync(dx, xh.data(), sizeof(float) * 4 * n, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(dt, th.data(), sizeof(float) * 8 * n, hipMemcpyHostToDevice, c->stream));
@@ -1347,9 +1376,6 @@ lbm_status lbm_mlp_train(lbm_ctx *c, const double *x, const double *lambda, int6
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (epoch_loss) epoch_loss[e] = lh / (double)nb;
   }
-  dev_release(c, dx);
-  dev_release(c, dt);
-  dev_release(c, dp);
   return LBM_OK;
 }
 

@@ -18,9 +18,14 @@ enum StorageKind { STO_FP64 = 0, STO_FP32 = 1, STO_FP16 = 2 };
 // atomics of all wavefronts of the device queued on a single line and took
 // two thirds of the D2Q21 collide's time.
 enum { CNT_NEWTON_CALLS = 0, CNT_NEWTON_ITERS = 1, CNT_NEWTON_FAIL = 2, CNT_NONFINITE = 3,
-       CNT_MLP_FALLBACK = 4, CNT_COUNT = 8, CNT_COPIES = 1024 };
+       CNT_MLP_FALLBACK = 4, CNT_HIST0 = 8, NHIST = 16, CNT_COUNT = 32, CNT_COPIES = 1024 };
 
 constexpr int NLAM = 8;
+// conserved sums: at most SUM_BLOCKS blocks per level, each striding over
+// the level's tiles, write one partial of the six quantities each; the
+// partials of level l start at l * SUM_BLOCKS * 6
+constexpr int SUM_BLOCKS = 1024, SUM_LEVELS = 8, SUM_Q = 6;
+constexpr int SUM_PARTIALS = SUM_LEVELS * SUM_BLOCKS * SUM_Q;
 constexpr int MLP_IN = 4, MLP_HID = 64, MLP_OUT = 8;
 
 struct FaceVals {
@@ -61,7 +66,8 @@ struct KArgs {
   Topo topo;
   const uint8_t *flags;
   const double *sigma, *rho_inf; // sponge (may be null)
-  float *lam;          // multipliers [8][stride] (DDF_NEWTON family)
+  void *lam;           // multipliers [8][stride] (DDF_NEWTON family): FP64 for
+                       // FP64 population storage, FP32 otherwise
   int64_t begin, count;
   PhysArgs ph;
   unsigned long long *counters;
@@ -74,7 +80,7 @@ struct CArgs {
   const void *gin_child;
   void *fout_coarse;      // newest buffer of the coarse level (virtual slots)
   void *gout_coarse;
-  float *lam;
+  void *lam;           // multipliers, element type as in KArgs
   int64_t stride, vbase;
   const int32_t *xnbr;      // exception rows (children of coarse ghosts have one)
   int64_t xstride;
@@ -93,7 +99,7 @@ struct EArgs {
   void *fout_fine;
   const void *gin_coarse;
   void *gout_fine;
-  float *lam;
+  void *lam;           // multipliers, element type as in KArgs
   int64_t stride;
   const int32_t *child, *ghost_cell;
   int64_t g0, count;
@@ -103,7 +109,7 @@ struct EArgs {
 struct BArgs {
   void *f;
   void *g;
-  float *lam;
+  void *lam;           // multipliers, element type as in KArgs
   int64_t stride;
   const int32_t *bc_cell, *bc_src;
   const int8_t *bc_face;
@@ -117,15 +123,15 @@ struct BArgs {
 struct MArgs {
   const void *fin;
   const void *gin;
-  const float *lam;
+  const void *lam;
   int64_t stride, vbase;
   Topo topo;
   const uint8_t *flags;
   const int32_t *cell_of;  // [slot] canonical cell, -1 for holes
   int64_t begin, count;    // slots
   double cs2w, uw[6][3], Cv;
-  int mode;            // 0: moments, 1: populations (+ multipliers), 2: sums,
-                       // 3: populations of listed cells
+  int mode;            // k_gather: 0 moments, 1 populations (+ multipliers),
+                       // 3 populations of listed cells (k_sums: sums)
   const int32_t *cells_list;  // mode 3: canonical cells, entries [list_begin, list_begin + count)
   const int32_t *slot_of;     // mode 3: slot of a canonical cell
   int64_t list_begin;
@@ -133,7 +139,7 @@ struct MArgs {
   double *lam_out;     // [8][n]
   int64_t n;
   double vol;          // cell volume 2^(-D l) for sums
-  double *partials;    // [blocks][6]
+  double *partials;    // k_sums: [gridDim.x][6] block partials
   int aa;              // 2: in-place buffer after an even step (rows swapped)
 };
 
@@ -141,7 +147,7 @@ struct MArgs {
 struct IArgs {
   void *f;
   void *g;
-  float *lam;
+  void *lam;           // multipliers, element type as in KArgs
   int64_t stride, n;
   const int32_t *slot_of;  // [n] slot of a canonical cell
   const double *src;   // moments [n_mom][n] or populations [Q][n]
@@ -157,10 +163,22 @@ struct Ops {
   void (*explode)(const EArgs &, hipStream_t);
   void (*bcfill)(const BArgs &, hipStream_t);
   void (*gather)(const MArgs &, bool pre, hipStream_t);
+  void (*sums)(const MArgs &, bool pre, hipStream_t);  // sum_blocks(a.count) blocks of k_sums
   void (*init)(const IArgs &, hipStream_t);
   void (*sensor)(const MArgs &, const PhysArgs &, bool pre, hipStream_t);
   int sizeof_storage;
 };
+
+// blocks of the k_sums launch over `count` slots
+inline int sum_blocks(int64_t count) {
+  const int64_t t = (count + 255) / 256;
+  return (int)(t < SUM_BLOCKS ? t : SUM_BLOCKS);
+}
+
+// final reduction of the conserved sums: out[k] = sum over levels l <
+// n_levels and blocks b < nb[l] of partials[(l * SUM_BLOCKS + b) * 6 + k],
+// in that order (one thread per quantity); enqueued on the stream
+void launch_sum_partials(const double *partials, const int *nb, int n_levels, double *out, hipStream_t s);
 
 bool get_ops_d2q9(int coll, int storage, Ops *out);
 bool get_ops_d3q27(int coll, int storage, Ops *out);

@@ -60,10 +60,11 @@ class MaskC(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("mass", C.c_double), ("momentum", C.c_double * 3), ("energy", C.c_double),
+                ("kinetic_energy", C.c_double),
                 ("updates", C.c_int64 * 8), ("newton_calls", C.c_int64),
                 ("newton_iterations", C.c_int64), ("newton_failures", C.c_int64),
                 ("mlp_fallbacks", C.c_int64), ("nonfinite_cells", C.c_int64),
-                ("coarse_steps", C.c_int64)]
+                ("coarse_steps", C.c_int64), ("newton_hist", C.c_int64 * 16)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -358,10 +359,11 @@ class LBM:
         s = Stats()
         self._check(self._L.lbm_stats_get(self.h, C.byref(s)), "lbm_stats_get")
         return dict(mass=s.mass, momentum=list(s.momentum)[: self.dim], energy=s.energy,
+                    kinetic_energy=s.kinetic_energy,
                     updates=list(s.updates)[: self.n_levels], newton_calls=s.newton_calls,
                     newton_iterations=s.newton_iterations, newton_failures=s.newton_failures,
                     mlp_fallbacks=s.mlp_fallbacks, nonfinite_cells=s.nonfinite_cells,
-                    coarse_steps=s.coarse_steps)
+                    coarse_steps=s.coarse_steps, newton_hist=list(s.newton_hist))
 
     def sync(self):
         self._check(self._L.lbm_sync(self.h), "lbm_sync")

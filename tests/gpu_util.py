@@ -36,7 +36,25 @@ def compare(m_gpu, m_ref, level, dim):
     out["u"] = float(np.sqrt(np.sum(vv * du ** 2)) / max(np.sqrt(np.sum(vv * uu ** 2)), 1e-300))
     if m_ref.shape[0] > 1 + dim:
         out["T"] = rel_l2(m_gpu[1 + dim], m_ref[1 + dim], vol)
+    # worst single cell, relative to the largest value of the field, so that a
+    # wrong corner or interface cell cannot hide in the volume-weighted norm
+    out["rho_max"] = float(np.max(np.abs(m_gpu[0][ok] - m_ref[0][ok])) / np.max(np.abs(m_ref[0][ok])))
+    dun = np.sqrt(sum((m_gpu[1 + d][ok] - m_ref[1 + d][ok]) ** 2 for d in range(dim)))
+    un = np.sqrt(sum(m_ref[1 + d][ok] ** 2 for d in range(dim)))
+    out["u_max"] = float(np.max(dun) / max(np.max(un), 1e-300))
+    if m_ref.shape[0] > 1 + dim:
+        out["T_max"] = float(np.max(np.abs(m_gpu[1 + dim][ok] - m_ref[1 + dim][ok])) / np.max(np.abs(m_ref[1 + dim][ok])))
     return out
+
+
+def assert_within(err, tol, tol_rho=None, cell=10.0):
+    """relative L2 of u and rho within their bounds, and the worst cell within
+    `cell` times the bound (relative to the field's largest value)"""
+    tr = tol if tol_rho is None else tol_rho
+    assert err["u"] <= tol and err["rho"] <= tr, err
+    assert err["u_max"] <= cell * tol and err["rho_max"] <= cell * tr, err
+    if "T" in err:
+        assert err["T"] <= tr and err["T_max"] <= cell * tr, err
 
 
 def run_pair(w, steps, storage, oracle_over=None, lib_over=None, schedule=True):

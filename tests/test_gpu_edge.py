@@ -1,12 +1,12 @@
 """GPU parity on the edge-case grids (partly filled bricks, wide stencils on
 ragged extents, a grid smaller than one brick that wraps everywhere, an
-empty refined level): FP64 storage against the oracle to relative L2 1e-12
-(D2Q21: 1e-11, the Newton tolerance)."""
+empty refined level): FP64 storage against the oracle to relative L2 1e-12,
+the Newton lattice (D2Q21) included."""
 import numpy as np
 import pytest
 
 from edge_cases import edge_cases
-from gpu_util import compare, run_pair, say
+from gpu_util import assert_within, compare, run_pair, say
 
 pytestmark = pytest.mark.gpu
 
@@ -21,8 +21,7 @@ def test_edge_grid_fp64_parity(name, w):
     mg, mo, level, s, o = run_pair(w, steps, storage)
     err = compare(mg, mo, level, w.dim)
     say(f"[edge] {name}: {s.n} cells {list(s.n_per_level)}: {err}")
-    tol = 1e-11 if w.collision == "DDF_NEWTON" else 1e-12
-    assert err["u"] <= tol and err["rho"] <= tol, err
+    assert_within(err, 1e-12)
     st = s.stats()
     counts = [int(n) for n in s.n_per_level]
     assert st["updates"] == [steps * (1 << l) * counts[l] for l in range(w.n_levels)]
