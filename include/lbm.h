@@ -240,6 +240,21 @@ typedef struct {
 /* Conservation sums and counters; synchronous. */
 lbm_status lbm_stats_get(lbm_ctx *ctx, lbm_stats *out);
 
+/* Allocation-free variant of the conservation sums of lbm_stats_get, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation).  Writes
+ * out_dev[6] = {mass, momentum x, y, z, total energy, kinetic energy}, the
+ * same values lbm_stats_get reports, bit for bit, into caller-owned device
+ * memory; enqueued on the context stream, no synchronisation, no device or
+ * host allocation.  The block partials live in a static device array of
+ * 8 x 1024 x 6 + 6 doubles (384 KiB) that each GPU holds until the process
+ * ends; every context on a GPU shares it, so calls that overlap on one GPU
+ * (two streams, or two threads) race and must be serialised by the caller.
+ * Limit: grids of at most 8 levels (any number of cells); more -> LBM_E_ARG.
+ * Errors: LBM_E_STATE before lbm_init, LBM_E_ARG for a null out_dev,
+ * LBM_E_DEVICE if the array's device address could not be obtained when
+ * the context was created, or a launch failed. */
+lbm_status lbm_sums_device(lbm_ctx *ctx, double *out_dev);
 
 /* Wait for all enqueued work; reports a latched numeric failure. */
 lbm_status lbm_sync(lbm_ctx *ctx);

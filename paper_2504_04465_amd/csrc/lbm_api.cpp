@@ -55,6 +55,8 @@ struct lbm_ctx {
   int32_t *d_cell_of = nullptr, *d_slot_of = nullptr, *d_crow = nullptr;
   uint8_t *d_flags = nullptr;
   double *d_sigma = nullptr, *d_rhoinf = nullptr;
+  double *d_sums_static = nullptr;     // this GPU's static partials array
+  hipError_t sums_static_err = hipSuccess;  // its address lookup at creation
   void *d_lam = nullptr;   // multipliers: FP64 with FP64 storage, else FP32
   int lam_bytes = 4;
   int32_t *d_ghost = nullptr, *d_child = nullptr;
@@ -496,6 +498,8 @@ lbm_status lbm_create(const lbm_params *params, lbm_dev_alloc_fn dev_alloc_fn,
   c->ddf = coll >= LBM_DDF_POLY;
   c->lamf = coll >= LBM_DDF_NEWTON;
   c->lam_bytes = c->p.storage == LBM_FP64 ? 8 : 4;
+  // address of the current GPU's static partials array (allocation-free sums)
+  if (!c->p.host_only) c->sums_static_err = sums_scratch(&c->d_sums_static);
   *out = c;
   return LBM_OK;
 }
@@ -1154,6 +1158,19 @@ static lbm_status enqueue_sums(lbm_ctx *c, double *partials, double *out) {
   }
   launch_sum_partials(partials, nb, c->L, out, c->stream);
   return check_launch(c);
+}
+
+lbm_status lbm_sums_device(lbm_ctx *c, double *out_dev) {
+  lbm_status s = need_state(c);
+  if (s != LBM_OK) return s;
+  if (!out_dev) return set_err(c, LBM_E_ARG, "null output");
+  if (c->L > SUM_LEVELS)
+    return set_err(c, LBM_E_ARG, "lbm_sums_device: grids of at most 8 levels (the static partials hold 8 x 1024 x 6)");
+  if (c->sums_static_err != hipSuccess || !c->d_sums_static)
+    return set_err(c, LBM_E_DEVICE, std::string("lbm_sums_device: no address for the static partials: ") +
+                                        hipGetErrorString(c->sums_static_err));
+  // partials in the static array, the result straight into the caller's buffer
+  return enqueue_sums(c, c->d_sums_static, out_dev);
 }
 
 lbm_status lbm_stats_get(lbm_ctx *c, lbm_stats *out) {

@@ -180,6 +180,10 @@ inline int sum_blocks(int64_t count) {
 // in that order (one thread per quantity); enqueued on the stream
 void launch_sum_partials(const double *partials, const int *nb, int n_levels, double *out, hipStream_t s);
 
+// device address of the current GPU's static array of SUM_PARTIALS + SUM_Q
+// doubles (looked up once per device, with that device current)
+hipError_t sums_scratch(double **out);
+
 bool get_ops_d2q9(int coll, int storage, Ops *out);
 bool get_ops_d3q27(int coll, int storage, Ops *out);
 bool get_ops_d2q21(int coll, int storage, Ops *out);

@@ -3,9 +3,38 @@
 // host read-back and the device-output entry point.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "ops.h"
 
 namespace lbm {
+
+// Partials and result of the allocation-free sums (lbm_sums_device): one
+// copy of this array per GPU, held until the process ends and shared by
+// every context on that GPU.  Host code never passes the array's name to a
+// kernel (on the host it is a stand-in, not a device address): it uses the
+// address sums_scratch() obtained for the current device.
+static __device__ __align__(256) double scratch[SUM_PARTIALS + SUM_Q];
+
+hipError_t sums_scratch(double **out) {
+  constexpr int MAX_DEV = 64;
+  static std::mutex mu;
+  static double *addr[MAX_DEV] = {};
+  *out = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEV) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = (double *)p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
 
 struct SumCounts {
   int nb[SUM_LEVELS];

@@ -27,6 +27,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_MASK", -3: "LBM_E_NOMEM", -4:
 # every entry point declared in include/lbm.h
 EXPORTS = ["lbm_create", "lbm_grid_build", "lbm_grid_info", "lbm_layout_info", "lbm_grid_export", "lbm_init",
            "lbm_step", "lbm_set_face_bc", "lbm_set_graphs", "lbm_moments", "lbm_moments_device", "lbm_stats_get",
+           "lbm_sums_device",
            "lbm_sync", "lbm_profile_enable", "lbm_profile_read", "lbm_get_state", "lbm_get_cells", "lbm_set_state",
            "lbm_remesh", "lbm_sensor",
            "lbm_last_error", "lbm_destroy", "lbm_mlp_set_weights", "lbm_mlp_get_weights",
@@ -95,6 +96,7 @@ def lib():
         L.lbm_moments.argtypes = [vp, vp]
         L.lbm_moments_device.argtypes = [vp, vp]
         L.lbm_stats_get.argtypes = [vp, C.POINTER(Stats)]
+        L.lbm_sums_device.argtypes = [vp, vp]
         L.lbm_sync.argtypes = [vp]
         L.lbm_profile_enable.argtypes = [vp, C.c_int]
         L.lbm_profile_read.argtypes = [vp, C.c_int, vp, vp, vp]
@@ -364,6 +366,12 @@ class LBM:
                     newton_iterations=s.newton_iterations, newton_failures=s.newton_failures,
                     mlp_fallbacks=s.mlp_fallbacks, nonfinite_cells=s.nonfinite_cells,
                     coarse_steps=s.coarse_steps, newton_hist=list(s.newton_hist))
+
+    def sums_device(self, out_ptr):
+        """conserved sums into the device buffer at out_ptr (6 doubles:
+        mass, momentum x/y/z, total energy, kinetic energy); enqueued only,
+        allocation-free"""
+        self._check(self._L.lbm_sums_device(self.h, C.c_void_p(int(out_ptr))), "lbm_sums_device")
 
     def sync(self):
         self._check(self._L.lbm_sync(self.h), "lbm_sync")
