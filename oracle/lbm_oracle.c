@@ -64,6 +64,7 @@ struct ol_sim {
   int32_t *bcsrc;
   int8_t *bcface;
   double *sigma, *rho_inf;
+  double *wall_du; /* [n][3] inflow noise on moving-wall links, or NULL */
   double tau[MAXL];
   /* state */
   int have_state;
@@ -649,12 +650,12 @@ ol_sim *ol_create(const ol_params *p) {
 static void free_grid(ol_sim *s) {
   free(s->xyz); free(s->lev); free(s->flag); free(s->nbr); free(s->ghost);
   free(s->child); free(s->bcsrc); free(s->bcface); free(s->sigma);
-  free(s->rho_inf);
+  free(s->rho_inf); free(s->wall_du);
   free(s->f); free(s->fs); free(s->g); free(s->gs); free(s->lam);
   free(s->collided);
   s->xyz = NULL; s->lev = NULL; s->flag = NULL; s->nbr = NULL;
   s->ghost = NULL; s->child = NULL; s->bcsrc = NULL; s->bcface = NULL;
-  s->sigma = NULL; s->rho_inf = NULL; s->f = NULL; s->fs = NULL;
+  s->sigma = NULL; s->rho_inf = NULL; s->wall_du = NULL; s->f = NULL; s->fs = NULL;
   s->g = NULL; s->gs = NULL; s->lam = NULL; s->collided = NULL;
   s->have_grid = 0; s->have_state = 0;
 }
@@ -1229,10 +1230,12 @@ static void collide_and_stream(ol_sim *s, int l) {
         int io = s->opp[i];
         fv = s->fs[c * Q + io];
         if (ddf) gv = s->gs[c * Q + io];
-        if (v <= -3) { /* Ladd's moving wall, wall density 1 */
+        if (v <= -3) { /* Ladd's moving wall, wall density 1; the wall
+                          velocity seen by this cell carries its inflow noise */
           const ol_face *F = &s->face[-3 - v];
           double cu = 0.0;
-          for (int d = 0; d < s->D; ++d) cu += s->c[i][d] * F->u[d];
+          for (int d = 0; d < s->D; ++d)
+            cu += s->c[i][d] * (F->u[d] + (s->wall_du ? s->wall_du[3 * c + d] : 0.0));
           fv += 2.0 * s->w[i] * cu / cs2w;
         }
       }
@@ -1385,6 +1388,18 @@ int ol_kinetic_energy(ol_sim *s, double *out) {
   *out = ksum_get(&K);
   free(f);
   free(g);
+  return 0;
+}
+
+int ol_set_inflow_noise(ol_sim *s, const double *du) {
+  if (!s->have_grid) return fail(s, -5, "no grid");
+  free(s->wall_du);
+  s->wall_du = NULL;
+  if (!du) return 0;
+  s->wall_du = (double *)malloc(s->n * 3 * sizeof(double));
+  if (!s->wall_du) return fail(s, -3, "out of memory");
+  for (int64_t c = 0; c < s->n; ++c)
+    for (int d = 0; d < 3; ++d) s->wall_du[3 * c + d] = du[d * s->n + c];
   return 0;
 }
 

@@ -72,6 +72,10 @@ int ol_sums(ol_sim *s, double *out); /* mass, momentum[D], energy (DDF) */
 /* sum of 2^(-D l) rho |u|^2 / 2 over the cells that are not fine ghosts */
 int ol_kinetic_energy(ol_sim *s, double *out);
 int ol_set_face(ol_sim *s, int face, const ol_face *f);
+/* per-cell perturbation of the moving-wall velocity ("inflow noise"):
+ * du SoA [3][n] in canonical cell order, added to the face velocity in the
+ * Ladd term of every moving-wall link of the cell; NULL removes it */
+int ol_set_inflow_noise(ol_sim *s, const double *du);
 int ol_counters(const ol_sim *s, int64_t *updates_per_level,
                 int64_t *newton_iters, int64_t *newton_calls);
 int ol_get_state(const ol_sim *s, double *f, double *g, double *lam);

@@ -73,6 +73,7 @@ def lib():
         L.ol_sums.argtypes = [vp, C.c_void_p]
         L.ol_kinetic_energy.argtypes = [vp, C.c_void_p]
         L.ol_set_face.argtypes = [vp, C.c_int, C.POINTER(Face)]
+        L.ol_set_inflow_noise.argtypes = [vp, C.c_void_p]
         L.ol_counters.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_void_p]
         L.ol_get_state.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_void_p]
         L.ol_set_state.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -225,6 +226,16 @@ class Oracle:
         out = np.zeros(2 + self.D)
         self._check(self._L.ol_sums(self.h, _ptr(out)))
         return out
+
+    def set_inflow_noise(self, du):
+        """du [3][n] (canonical order) added to the moving-wall velocity seen
+        by each cell; None removes it"""
+        if du is None:
+            self._check(self._L.ol_set_inflow_noise(self.h, None))
+            return
+        d = np.ascontiguousarray(du, dtype=np.float64)
+        assert d.shape == (3, self.n)
+        self._check(self._L.ol_set_inflow_noise(self.h, _ptr(d)))
 
     def kinetic_energy(self):
         out = C.c_double()

@@ -246,3 +246,43 @@ def test_neumann_one_step_non_uniform_closed_form(lattice, collision):
     bc = np.nonzero(src != np.arange(o.n))[0]
     feq_own = np.array([o.feq(m0[0, c], m0[1:3, c], m0[3, c] if ddf else 0.0)[0] for c in bc])
     assert np.min(np.max(np.abs(Pf[bc] - feq_own), axis=1)) > 1e-5
+
+
+def test_moving_wall_inflow_noise_one_step():
+    """Ladd's moving wall (wall density 1) with a per-cell perturbation of
+    the wall velocity (the cylinder's inflow noise): from a fluid at rest
+    (post-collision state w_i), after one step every population that crosses
+    the moving face equals w_opp + 2 w_i xi_i . (u_w + du_c) / cs2, every
+    population that crosses the resting wall w_opp, and every other one w_i;
+    the perturbation of other cells plays no part.  A dropped or reversed
+    perturbation fails."""
+    nx, ny = 8, 6
+    uw = np.array([0.05, 0.01, 0.0])
+    w = channel("D2Q9", "BGK", nx, ny, [W.Face("moving_wall", u=tuple(uw)), W.Face("wall")])
+    w.init = uniform(1.0, (0.0, 0.0), 0.0, False)
+    o = Oracle.from_workload(w)
+    o.init_workload(w)
+    e = o.export()
+    r = np.random.default_rng(3)
+    du = np.zeros((3, o.n))
+    du[:2] = 1e-3 * (2 * r.random((2, o.n)) - 1)
+    o.set_inflow_noise(du)
+    o.step(1)
+    f, _, _ = o.state()
+    x = e["coords"][:, 0]
+    exp = np.tile(o.w, (o.n, 1))
+    for i in range(1, o.Q):
+        j = o.opp[i]
+        src = x - o.c[i][0]
+        left = src < 0
+        right = src >= nx
+        cu = o.c[i][0] * (uw[0] + du[0]) + o.c[i][1] * (uw[1] + du[1])
+        exp[left, i] = o.w[j] + 2 * o.w[i] * cu[left] / o.cs2
+        exp[right, i] = o.w[j]
+    assert np.max(np.abs(f - exp)) < 1e-15
+    # the perturbation matters at the size it is given
+    o2 = Oracle.from_workload(w)
+    o2.init_workload(w)
+    o2.step(1)
+    f2, _, _ = o2.state()
+    assert np.max(np.abs(f - f2)) > 1e-4
