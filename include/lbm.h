@@ -210,6 +210,29 @@ lbm_status lbm_set_face_bc(lbm_ctx *ctx, int face, const lbm_face_bc *bc);
  * (capture is refused there and lbm_step launches as usual). */
 lbm_status lbm_set_graphs(lbm_ctx *ctx, int on);
 
+/* Concurrent levels (Sec. 4.5; the paper's remedy for small levels that
+ * leave most of the GPU idle): with on != 0 (the default) every substep
+ * at which two or more levels are active runs their collide-and-stream
+ * updates as one launch whose blocks span all those levels, after the
+ * substep's coalescences and before its boundary fills and explosions;
+ * results are identical to per-level launches.  Used where the model has
+ * it (BGK, RR and the polynomial double distribution; the Newton and
+ * surrogate models keep per-level launches), with two buffers, and not
+ * while kernel timing is enabled (timing is per level).  Errors: LBM_E_ARG
+ * for a null context. */
+lbm_status lbm_set_level_fusion(lbm_ctx *ctx, int on);
+
+/* Inflow noise (the seeded perturbation of the cylinder's inflow): du, a
+ * host array [3][n_cells] in canonical cell order, is added per cell to the
+ * face velocity in Ladd's moving-wall term (App. A.3) of every moving-wall
+ * link of the cell; other cells ignore their entries.  The values are
+ * caller-owned and copied; NULL removes the perturbation.  A new grid
+ * (lbm_grid_build, lbm_remesh) starts without it.  Synchronous.  Errors:
+ * LBM_E_STATE without a grid on the device, LBM_E_ARG for non-finite
+ * values, LBM_E_UNSUPPORTED with in-place streaming or the Newton /
+ * surrogate equilibria, LBM_E_NOMEM, LBM_E_DEVICE. */
+lbm_status lbm_set_inflow_noise(lbm_ctx *ctx, const double *du);
+
 /* Macroscopic fields of the state at the synchronisation point (pre-
  * collision populations, coarse ghosts with coalesced unknowns; fine ghosts
  * are NaN), written to the host array out [n_mom][n_cells].  Synchronous. */

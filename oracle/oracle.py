@@ -208,6 +208,8 @@ class Oracle:
     def init_workload(self, w):
         e = self.export()
         self.init(w.initial_moments(e["coords"], e["level"]))
+        if getattr(w, "inflow_noise", None) is not None:
+            self.set_inflow_noise(w.inflow_noise(e["coords"], e["level"]))
 
     def step(self, n=1):
         self._check(self._L.ol_step(self.h, n))

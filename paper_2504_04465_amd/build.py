@@ -20,6 +20,11 @@ CXX_SOURCES = ["grid_builder.cpp", "layout.cpp", "remesh.cpp", "lbm_api.cpp"]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+# per-unit flags: the surrogate's matrix products accumulate in ordinary
+# VGPRs (not AGPRs), so that the collide holding the Newton state next to
+# them keeps two wavefronts per SIMD
+UNIT_FLAGS = {"k_d2q21.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+              "mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-fopenmp", "-D__HIP_PLATFORM_AMD__",
              "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-I" + os.path.join(ROCM, "include")]
 
@@ -58,7 +63,8 @@ def build(verbose: bool = False, jobs: int = 8, incremental: bool = False) -> st
     for s in HIP_SOURCES:
         o = os.path.join(BUILD, s.replace(".hip", ".o"))
         if not incremental or _stale(o, os.path.join(CSRC, s)):
-            cmds.append([os.path.join(ROCM, "bin", "hipcc")] + HIPCC_FLAGS + ["-c", os.path.join(CSRC, s), "-o", o])
+            cmds.append([os.path.join(ROCM, "bin", "hipcc")] + HIPCC_FLAGS + UNIT_FLAGS.get(s, [])
+                        + ["-c", os.path.join(CSRC, s), "-o", o])
         objs.append(o)
     for s in CXX_SOURCES:
         o = os.path.join(BUILD, s.replace(".cpp", ".o"))

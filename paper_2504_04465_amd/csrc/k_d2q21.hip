@@ -9,8 +9,10 @@
 namespace lbm {
 using L21 = Lattice<LAT_D2Q21>;
 
-// Collide-and-stream with the surrogate: every wavefront evaluates the MLP
-// for its 64 cells (two 32-cell tiles on the matrix cores), then each cell
+// Collide-and-stream with the surrogate: the block stages the network's
+// weights in LDS once, every wavefront evaluates the MLP for its 64 cells
+// (two 32-cell tiles on the matrix cores, activations kept in registers
+// between the layers), then each cell
 // takes the predicted multipliers (DDF_MLP), or one Newton correction from
 // them with a full Newton fallback above fallback_tol (DDF_MLP_NEWTON).
 // The populations are pulled twice: for the moments, and again (from the
@@ -22,10 +24,7 @@ __global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
   using L = L21;
   using C = typename Sto<S>::C;
   constexpr int Q = L::Q;
-  __shared__ __align__(16) __bf16 xin[BLOCK / 64][2][32 * 16];
-  __shared__ __align__(16) __bf16 ha[BLOCK / 64][32 * 64];
-  __shared__ __align__(16) __bf16 hb[BLOCK / 64][32 * 64];
-  __shared__ float yb[BLOCK / 64][2][32 * 8];
+  __shared__ MlpInfer W;
   __shared__ uint32_t nbs[BLOCK / 64][Brick<L>::NBP];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t t = xcd_block() * BLOCK + threadIdx.x;
@@ -38,29 +37,29 @@ __global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
   C rho = (C)1, u[3] = {(C)0, (C)0, (C)0}, T = (C)1;
   if (valid) {
     C f[Q], g[Q];
-    gather<L, S, PRE, true>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[w], stride, a.vbase, c, l, brick,
+    gather<L, S, PRE, true, 0, false>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[w], stride, a.vbase, c, l, brick,
                             a.topo.xmask[brick], a.ph.uw, a.ph.cs2w, f, g);
     cell_moments<L, C, true>(f, g, (C)a.ph.Cv, rho, u, T);
   }
   // the populations again, after the equilibrium (no code motion across)
   auto pull = [&](C *f, C *g) {
     asm volatile("" ::: "memory");
-    gather<L, S, PRE, true>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[w], stride, a.vbase, c, l, brick,
+    gather<L, S, PRE, true, 0, false>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[w], stride, a.vbase, c, l, brick,
                             a.topo.xmask[brick], a.ph.uw, a.ph.cs2w, f, g);
   };
   const bool collide = valid && !(fl & (F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ));
   // the multipliers depend on (u, T) only; non-colliding lanes feed a benign state
   float cux = collide ? (float)u[0] : 0.0f, cuy = collide ? (float)u[1] : 0.0f;
   const Canon cn = canonical(cux, cuy);
-  mlp_input_row(&xin[w][l >> 5][(l & 31) * 16], collide ? (float)rho : 1.0f, cux, cuy, collide ? (float)T : 1.0f);
-  __syncthreads();
   const MlpOperands *P = (const MlpOperands *)a.ph.mlp;
-#pragma unroll
-  for (int tile = 0; tile < 2; ++tile) mlp_forward_tile(P, xin[w][tile], ha[w], hb[w], ha[w], yb[w][tile], nullptr);
+  stage_infer(&P->inf, &W);
+  float xin[4], y[8];
+  mlp_normalise(collide ? (float)rho : 1.0f, cux, cuy, collide ? (float)T : 1.0f, xin);
+  mlp_infer_wave(W, xin, y);
   if (collide) {
     double lam[NLAM];
 #pragma unroll
-    for (int k = 0; k < NLAM; ++k) lam[k] = (double)P->mu[k] + (double)P->sig[k] * (double)yb[w][l >> 5][(l & 31) * 8 + k];
+    for (int k = 0; k < NLAM; ++k) lam[k] = (double)P->mu[k] + (double)P->sig[k] * (double)y[k];
     uncanonical(cn, lam);
     C rhop = rho;
     if (fl & F_SPONGE) {

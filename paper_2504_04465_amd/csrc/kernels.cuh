@@ -83,11 +83,11 @@ using LamT = typename LamOf<S>::T;
 
 // Blocks are dealt to the 8 XCDs round-robin; remap so that each XCD works
 // on one contiguous range of Z-ordered cells and its L2 sees the neighbours.
-__device__ inline int64_t xcd_block() {
-  const uint32_t nb = gridDim.x, b = blockIdx.x;
+__device__ inline int64_t xcd_map(uint32_t b, uint32_t nb) {
   const uint32_t q = nb >> 3, r = nb & 7u, x = b & 7u, loc = b >> 3;
   return (int64_t)x * q + (x < r ? x : r) + loc;
 }
+__device__ inline int64_t xcd_block() { return xcd_map(blockIdx.x, gridDim.x); }
 
 template <int W, class T>
 __device__ inline T group_sum(T v) {
@@ -110,6 +110,13 @@ __device__ inline double wall_dot(const double (&uw)[6][3], int k, int i) {
   for (int f = 0; f < 6; ++f)
     if (f == k) r = cx_<L>(i, 0) * uw[f][0] + cx_<L>(i, 1) * uw[f][1] + cx_<L>(i, 2) * uw[f][2];
   return r;
+}
+
+// the cell's perturbation of the moving-wall velocity (inflow noise)
+// projected on xi_i: xdu holds [Q-1][xstride] per explicit row, or is null;
+// read only on a moving-wall link
+__device__ inline double noise_dot(const double *xdu, int64_t xstride, int64_t row, int i) {
+  return xdu ? xdu[(int64_t)(i - 1) * xstride + row] : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -147,10 +154,11 @@ __device__ inline int lane_bits(int p, int d) {
 // AA = 2: the single in-place buffer after an even step holds cell x's
 // post-collision population i in row opp(i); pulls swap the rows (a wall
 // returns the cell's own row i).
-template <class L, class S, bool PRE, bool DDF, int AA = 0>
+template <class L, class S, bool PRE, bool DDF, int AA = 0, bool NZ = true>
 __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnbr, int64_t xstride, int64_t row,
                                   int64_t stride, int64_t vbase, int64_t c, const double (&uw)[6][3], double cs2w,
-                                  typename Sto<S>::C *f, typename Sto<S>::C *g, uint64_t want = ~0ull) {
+                                  typename Sto<S>::C *f, typename Sto<S>::C *g, uint64_t want = ~0ull,
+                                  const double *xdu = nullptr) {
   using C = typename Sto<S>::C;
   int32_t sv[L::Q];
 #pragma unroll
@@ -170,7 +178,9 @@ __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnb
   if (!PRE) {
 #pragma unroll
     for (int i = 1; i < L::Q; ++i)
-      if (((want >> i) & 1ull) && sv[i] <= -2) f[i] += (C)(2.0 * L::S.w[i] * wall_dot<L>(uw, -2 - sv[i], i) / cs2w);
+      if (((want >> i) & 1ull) && sv[i] <= -2)
+        f[i] += (C)(2.0 * L::S.w[i] * (wall_dot<L>(uw, -2 - sv[i], i) + (NZ ? noise_dot(xdu, xstride, row, i) : 0.0)) /
+                    cs2w);
   }
 }
 
@@ -187,7 +197,7 @@ __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnb
 //
 // Lanes flagged in the brick's exception mask read their explicit row:
 // every source is loaded before any is used, so the loads overlap.
-template <class L, class S, bool PRE, bool DDF, int AA = 0>
+template <class L, class S, bool PRE, bool DDF, int AA = 0, bool NZ = true>
 __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const uint32_t *nbs, int64_t stride,
                               int64_t vbase, int64_t c, int lane, int32_t brick, uint64_t xm,
                               const double (&uw)[6][3], double cs2w, typename Sto<S>::C *f,
@@ -234,7 +244,8 @@ __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const 
     }
   } else {
     const int64_t row = tp.xbase[brick] + __popcll(xm & ((1ull << lane) - 1ull));
-    gather_row<L, S, PRE, DDF, AA>(fin, gin, tp.xnbr, tp.xstride, row, stride, vbase, c, uw, cs2w, f, g);
+    gather_row<L, S, PRE, DDF, AA, NZ>(fin, gin, tp.xnbr, tp.xstride, row, stride, vbase, c, uw, cs2w, f, g, ~0ull,
+                                       tp.xdu);
   }
 }
 
@@ -290,7 +301,8 @@ __device__ inline void push_store(S *fout, S *gout, const Topo &tp, const uint32
         if (DDF) Sto<S>::stn(gout, (int64_t)i * stride + s, g[i], 0.0);
       } else {
         C v = f[i];
-        if (s <= -2) v += (C)(2.0 * L::S.w[j] * wall_dot<L>(uw, -2 - s, j) / cs2w);
+        if (s <= -2)
+          v += (C)(2.0 * L::S.w[j] * wall_dot<L>(uw, -2 - s, j) / cs2w);  // no inflow noise in place
         Sto<S>::stn(fout, (int64_t)j * stride + c, v, L::S.w[j]);
         if (DDF) Sto<S>::stn(gout, (int64_t)j * stride + c, g[i], 0.0);
       }
@@ -1010,7 +1022,15 @@ struct CollideBlock {
 // AA selects in-place streaming on one buffer (a.fin == a.fout): 1 = even
 // step (read the cell's own rows, write population i to its row opp(i)),
 // 2 = odd step (pull from the swapped rows, push to the neighbours).
-template <class L, int COLL, class S, bool PRE, int AA = 0>
+//
+// With a.multi.n > 0 one launch updates every level active at a substep
+// (the paper's remedy for small levels that leave most of the GPU idle,
+// Sec. 4.5): the grid is the concatenation of the levels' blocks, each
+// level's range starting at a multiple of 8 blocks so that the round-robin
+// XCD dispatch keeps its per-XCD contiguous order inside the level; a block
+// takes its level's buffers, cell range and relaxation time from the table
+// and runs the same update as a per-level launch.
+template <class L, int COLL, class S, bool PRE, int AA = 0, bool NZ = false>
 __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
     __attribute__((amdgpu_waves_per_eu(MinWaves<L, COLL, S>::value))) k_collide(const KArgs a) {
   using C = typename Sto<S>::C;
@@ -1018,19 +1038,44 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
   constexpr int Q = L::Q;
   constexpr int CB = CollideBlock<L, COLL>::value;
   __shared__ uint32_t nbs[CB / 64][Brick<L>::NBP];
-  const int64_t t = xcd_block() * CB + threadIdx.x;
-  const bool live = t < a.count;  // whole wavefronts
-  const int64_t c = a.begin + (live ? t : 0);
+  int64_t blk, begin = a.begin, count = a.count;
+  const void *fin_p = a.fin, *gin_p = a.gin;
+  void *fout_p = a.fout, *gout_p = a.gout;
+  double tau = a.ph.tau;
+  bool multi = false;
+  if constexpr (!PRE && AA == 0 && COLL < COLL_DDF_NEWTON) multi = a.multi.n > 0;
+  if (multi) {
+    const int64_t b = blockIdx.x;
+    int k = 0;
+#pragma unroll
+    for (int j = 1; j < MAX_LEVELS; ++j)
+      if (j < a.multi.n && b >= a.multi.block0[j]) k = j;
+    blk = xcd_map((uint32_t)(b - a.multi.block0[k]), (uint32_t)(a.multi.block0[k + 1] - a.multi.block0[k]));
+    begin = a.multi.begin[k];
+    count = a.multi.count[k];
+    tau = a.multi.tau[k];
+    const int p = a.multi.parity[k];
+    fin_p = a.multi.f[p];
+    fout_p = (void *)a.multi.f[1 - p];
+    gin_p = a.multi.g[p];
+    gout_p = (void *)a.multi.g[1 - p];
+    if (blk * CB >= count) return;  // padding blocks of the level
+  } else {
+    blk = xcd_block();
+  }
+  const int64_t t = blk * CB + threadIdx.x;
+  const bool live = t < count;  // whole wavefronts
+  const int64_t c = begin + (live ? t : 0);
   const int32_t brick = stage_bricks<L, S>(a.topo, nbs, c, live);
   if (!live) return;
   const uint8_t fl = a.flags[c];
   if (fl & F_HOLE) return;
   const int64_t stride = a.stride;
-  const S *fin = (const S *)a.fin;
-  const S *gin = (const S *)a.gin;
+  const S *fin = (const S *)fin_p;
+  const S *gin = (const S *)gin_p;
   C f[Q];
   C g[DDF ? Q : 1];
-  gather<L, S, PRE || AA == 1, DDF, AA == 2 ? 2 : 0>(fin, gin, a.topo, nbs[threadIdx.x >> 6], stride, a.vbase, c,
+  gather<L, S, PRE || AA == 1, DDF, AA == 2 ? 2 : 0, NZ>(fin, gin, a.topo, nbs[threadIdx.x >> 6], stride, a.vbase, c,
                                                    threadIdx.x & 63, brick, a.topo.xmask[brick], a.ph.uw,
                                                    a.ph.cs2w, f, g);
   if (!(fl & (F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ))) {
@@ -1046,7 +1091,7 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
       C feq[Q];
       if constexpr (product_basis<L>()) equilibrium_product<L, C>(rhop, u, feq);
       else equilibrium_hermite3<L, C>(rhop, u, feq);
-      const C om = (C)(1.0 / a.ph.tau);
+      const C om = (C)(1.0 / tau);
 #pragma unroll
       for (int i = 0; i < Q; ++i) f[i] = f[i] - om * (f[i] - feq[i]);
     } else if constexpr (COLL == COLL_RR) {
@@ -1069,9 +1114,9 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
 #pragma unroll
         for (int y = 0; y < x; ++y) P[x][y] = P[y][x];
       if constexpr (product_basis<L>())
-        rr_product<L, C>(f, rho, rhop, u, P, (C)(1.0 - 1.0 / a.ph.tau), a.ph.trace_eq != 0);
+        rr_product<L, C>(f, rho, rhop, u, P, (C)(1.0 - 1.0 / tau), a.ph.trace_eq != 0);
       else
-        rr_hermite3<L, C>(f, rho, rhop, u, P, (C)(1.0 - 1.0 / a.ph.tau), a.ph.trace_eq != 0);
+        rr_hermite3<L, C>(f, rho, rhop, u, P, (C)(1.0 - 1.0 / tau), a.ph.trace_eq != 0);
     } else {
       C feq[Q], geq[Q];
       double lam[NLAM];
@@ -1109,7 +1154,7 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
 #pragma unroll
         for (int k = 0; k < NLAM; ++k) ((LamT<S> *)a.lam)[(int64_t)k * stride + c] = (LamT<S>)lam[k];
       }
-      C te = (C)a.ph.tau;
+      C te = (C)tau;
       if (a.ph.sensor_on) te *= sensor_alpha<L, C>(f, feq, te, (C)a.ph.sensor_A);
       const C om = (C)1 / te;
 #pragma unroll
@@ -1119,8 +1164,8 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
       }
     }
   }
-  S *fout = (S *)a.fout;
-  S *gout = (S *)a.gout;
+  S *fout = (S *)fout_p;
+  S *gout = (S *)gout_p;
   if constexpr (AA == 2) {
     push_store<L, S, DDF>(fout, gout, a.topo, nbs[threadIdx.x >> 6], stride, c, threadIdx.x & 63, brick,
                           a.topo.xmask[brick], a.ph.uw, a.ph.cs2w, f, g);
@@ -1182,7 +1227,9 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
         else idx = sv >= 0 ? (int64_t)i * a.stride + sv : (int64_t)L::S.opp[i] * a.stride + ch;
         v = Sto<S>::ld(fin, idx, L::S.w[i]);
         if (DDF) vg = Sto<S>::ld(gin, idx, 0.0);
-        if (!PRE && sv <= -2) v += (C)(2.0 * L::S.w[i] * wall_dot<L>(a.uw, -2 - sv, i) / a.cs2w);
+        if (!PRE && sv <= -2)
+          v += (C)(2.0 * L::S.w[i] * (wall_dot<L>(a.uw, -2 - sv, i) + noise_dot(a.xdu, a.xstride, crow, i)) /
+                   a.cs2w);
       }
       v = group_sum<NCH, C>(v);
       if (DDF) vg = group_sum<NCH, C>(vg);
@@ -1196,7 +1243,8 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
     // (every child of a coarse ghost has an explicit row), all loads first
     C f[L::Q], g[DDF ? L::Q : 1];
     if (ch >= 0)
-      gather_row<L, S, PRE, DDF>(fin, gin, a.xnbr, a.xstride, crow, a.stride, a.vbase, ch, a.uw, a.cs2w, f, g, mask);
+      gather_row<L, S, PRE, DDF>(fin, gin, a.xnbr, a.xstride, crow, a.stride, a.vbase, ch, a.uw, a.cs2w, f, g, mask,
+                                 a.xdu);
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
       const bool need = (mask >> i) & 1ull;
@@ -1561,8 +1609,26 @@ struct Launch {
     const unsigned nb = (unsigned)((a.count + CB - 1) / CB);
     if (a.aa == 1) hipLaunchKernelGGL((k_collide<L, COLL, S, false, 1>), dim3(nb), dim3(CB), 0, s, a);
     else if (a.aa == 2) hipLaunchKernelGGL((k_collide<L, COLL, S, false, 2>), dim3(nb), dim3(CB), 0, s, a);
-    else if (pre) hipLaunchKernelGGL((k_collide<L, COLL, S, true>), dim3(nb), dim3(CB), 0, s, a);
+    else if (noisy(a)) {
+      // inflow noise on the moving-wall links: separate instantiations, so
+      // that the others keep their registers
+      if constexpr (COLL < COLL_DDF_NEWTON) {
+        if (pre) hipLaunchKernelGGL((k_collide<L, COLL, S, true, 0, true>), dim3(nb), dim3(CB), 0, s, a);
+        else hipLaunchKernelGGL((k_collide<L, COLL, S, false, 0, true>), dim3(nb), dim3(CB), 0, s, a);
+      }
+    } else if (pre) hipLaunchKernelGGL((k_collide<L, COLL, S, true>), dim3(nb), dim3(CB), 0, s, a);
     else hipLaunchKernelGGL((k_collide<L, COLL, S, false>), dim3(nb), dim3(CB), 0, s, a);
+  }
+  static bool noisy(const KArgs &a) { return a.topo.xdu != nullptr; }
+  static void collide_multi(const KArgs &a, hipStream_t s) {
+    if constexpr (COLL < COLL_DDF_NEWTON) {
+      constexpr int CB = CollideBlock<L, COLL>::value;
+      const dim3 grid((unsigned)a.multi.block0[a.multi.n]);
+      if (a.multi.n > 0 && a.multi.block0[a.multi.n] > 0) {
+        if (noisy(a)) hipLaunchKernelGGL((k_collide<L, COLL, S, false, 0, true>), grid, dim3(CB), 0, s, a);
+        else hipLaunchKernelGGL((k_collide<L, COLL, S, false>), grid, dim3(CB), 0, s, a);
+      }
+    }
   }
   static void coalesce(const CArgs &a0, bool pre, hipStream_t s) {
     if (a0.count <= 0) return;
@@ -1611,6 +1677,8 @@ struct Launch {
     Ops o;
     o.sensor = &sensor;
     o.collide = &collide;
+    o.collide_multi = COLL < COLL_DDF_NEWTON ? &collide_multi : nullptr;
+    o.collide_block = CollideBlock<L, COLL>::value;
     o.coalesce = &coalesce;
     o.explode = &explode;
     o.bcfill = &bcfill;

@@ -51,6 +51,7 @@ struct lbm_ctx {
   std::vector<void *> allocs;
   void *f[2]{}, *gb[2]{};
   int32_t *d_nbrick = nullptr, *d_xbase = nullptr, *d_xnbr = nullptr;
+  double *d_xdu = nullptr;  // xi_i . inflow noise per explicit row [Q-1][xstride], or null
   uint64_t *d_xmask = nullptr;
   int32_t *d_cell_of = nullptr, *d_slot_of = nullptr, *d_crow = nullptr;
   uint8_t *d_flags = nullptr;
@@ -80,6 +81,9 @@ struct lbm_ctx {
   bool have_mlp = false;
   // graph replay of two coarse steps (launch-bound grids)
   bool use_graphs = false;
+  // one collide launch for all levels active at a substep (on by default
+  // where the model has it)
+  bool fuse_levels = true;
   hipGraphExec_t gexec = nullptr;
   int gparity[8]{};
   // profiling
@@ -134,6 +138,7 @@ void free_device(lbm_ctx *c) {
   c->allocs.clear();
   c->f[0] = c->f[1] = c->gb[0] = c->gb[1] = nullptr;
   c->d_nbrick = c->d_xbase = c->d_xnbr = nullptr;
+  c->d_xdu = nullptr;
   c->d_xmask = nullptr;
   c->d_cell_of = c->d_slot_of = c->d_crow = nullptr;
   c->d_flags = nullptr;
@@ -218,6 +223,7 @@ Topo topo(const lbm_ctx *c) {
   t.xbase = c->d_xbase;
   t.xnbr = c->d_xnbr;
   t.xstride = c->lay.xstride;
+  t.xdu = c->d_xdu;
   return t;
 }
 
@@ -234,6 +240,7 @@ void launch_coalesce(lbm_ctx *c, int l) {
   a.vbase = c->NS;
   a.xnbr = c->d_xnbr;
   a.xstride = c->lay.xstride;
+  a.xdu = c->d_xdu;
   a.child = c->d_child;
   a.crow = c->d_crow;
   a.unknown = c->d_unknown;
@@ -304,25 +311,31 @@ hipEvent_t take_event(lbm_ctx *c) {
   return e;
 }
 
+// argument block of level l's collide reading buffer par
+KArgs collide_args(lbm_ctx *c, int l, int par) {
+  KArgs a{};
+  a.fin = c->f[par];
+  a.fout = c->f[1 - par];
+  a.gin = c->gb[par];
+  a.gout = c->gb[1 - par];
+  a.stride = c->stride;
+  a.vbase = c->NS;
+  a.topo = topo(c);
+  a.flags = c->d_flags;
+  a.sigma = c->d_sigma;
+  a.rho_inf = c->d_rhoinf;
+  a.lam = c->d_lam;
+  a.begin = c->lay.soff[l];
+  a.count = c->lay.soff[l + 1] - c->lay.soff[l];
+  a.ph = phys(c, l);
+  a.counters = c->d_counters;
+  return a;
+}
+
 void launch_collide(lbm_ctx *c, int l) {
   const int64_t cnt = c->lay.soff[l + 1] - c->lay.soff[l];
   if (cnt > 0) {
-    KArgs a{};
-    a.fin = c->f[c->parity[l]];
-    a.fout = c->f[1 - c->parity[l]];
-    a.gin = c->gb[c->parity[l]];
-    a.gout = c->gb[1 - c->parity[l]];
-    a.stride = c->stride;
-    a.vbase = c->NS;
-    a.topo = topo(c);
-    a.flags = c->d_flags;
-    a.sigma = c->d_sigma;
-    a.rho_inf = c->d_rhoinf;
-    a.lam = c->d_lam;
-    a.begin = c->lay.soff[l];
-    a.count = cnt;
-    a.ph = phys(c, l);
-    a.counters = c->d_counters;
+    KArgs a = collide_args(c, l, c->parity[l]);
     ProfSlot slot{};
     if (c->prof) {
       slot.a = take_event(c);
@@ -929,9 +942,71 @@ lbm_status lbm_remesh(lbm_ctx *c, const lbm_mask *refine, const lbm_mask *solid)
 namespace {
 
 // one coarse step: 2^(L-1) finest substeps, active levels coarsest first
+// whether a substep's collides can go in one launch: the model has the
+// fused kernel, the argument blocks are on the device, the levels read
+// post-collision input from two buffers, and no launch is being timed
+bool fused_ok(const lbm_ctx *c, int t) {
+  if (!c->fuse_levels || !c->ops.collide_multi || c->prof || c->p.in_place) return false;
+  int n = 0;
+  for (int l = 0; l < c->L; ++l) {
+    if (t % (1 << (c->L - 1 - l)) != 0) continue;
+    if (c->pre[l]) return false;
+    ++n;
+  }
+  return n >= 2;
+}
+
+// the collides of the active levels of substep t in one launch; buffer
+// parities, update counts and pre-collision flags as launch_collide leaves them
+void launch_collide_fused(lbm_ctx *c, int t) {
+  int lv[MAX_LEVELS], n = 0;
+  for (int l = 0; l < c->L; ++l)
+    if (t % (1 << (c->L - 1 - l)) == 0) lv[n++] = l;
+  KArgs a = collide_args(c, lv[0], c->parity[lv[0]]);
+  MultiTable &m = a.multi;
+  for (int p = 0; p < 2; ++p) {
+    m.f[p] = c->f[p];
+    m.g[p] = c->gb[p];
+  }
+  int64_t nb = 0;
+  const int cb = c->ops.collide_block;
+  for (int k = 0; k < n; ++k) {
+    const int l = lv[k];
+    m.parity[k] = c->parity[l];
+    m.begin[k] = c->lay.soff[l];
+    m.count[k] = c->lay.soff[l + 1] - c->lay.soff[l];
+    m.tau[k] = c->tau[l];
+    m.block0[k] = nb;
+    nb += ((m.count[k] + cb - 1) / cb + 7) / 8 * 8;  // a multiple of 8 blocks per level
+  }
+  m.block0[n] = nb;
+  m.n = n;
+  c->ops.collide_multi(a, c->stream);
+  for (int k = 0; k < n; ++k) {
+    const int l = lv[k];
+    c->updates[l] += c->g.off[l + 1] - c->g.off[l];
+    c->parity[l] ^= 1;
+    c->pre[l] = false;
+  }
+}
+
 void coarse_step(lbm_ctx *c) {
   const int L = c->L;
   for (int t = 0; t < (1 << (L - 1)); ++t) {
+    if (fused_ok(c, t)) {
+      // coalescences (each reads the finer level's state of the previous
+      // substep), the collides of all active levels at once, then the
+      // boundary fills and explosions in the per-level order
+      for (int l = 0; l + 1 < L; ++l)
+        if (t % (1 << (L - 1 - l)) == 0) launch_coalesce(c, l);
+      launch_collide_fused(c, t);
+      for (int l = 0; l < L; ++l) {
+        if (t % (1 << (L - 1 - l)) != 0) continue;
+        launch_bcfill(c, l);
+        if (l > 0 && t % (1 << (L - l)) == 0) launch_explode(c, l - 1);
+      }
+      continue;
+    }
     for (int l = 0; l < L; ++l) {
       if (t % (1 << (L - 1 - l)) != 0) continue;
       if (l + 1 < L) launch_coalesce(c, l);
@@ -942,6 +1017,8 @@ void coarse_step(lbm_ctx *c) {
   }
   c->coarse_steps++;
 }
+
+
 
 // Two coarse steps as one HIP graph: after two steps every level's buffer
 // parity is back where it was (level l flips 2^(l+1) times), so the
@@ -1018,6 +1095,49 @@ lbm_status lbm_set_graphs(lbm_ctx *c, int on) {
   if (!c) return LBM_E_ARG;
   c->use_graphs = on != 0;
   if (!c->use_graphs) drop_graph(c);
+  return LBM_OK;
+}
+
+lbm_status lbm_set_inflow_noise(lbm_ctx *c, const double *du) {
+  if (!c) return LBM_E_ARG;
+  if (c->p.host_only || !c->have_grid) return set_err(c, LBM_E_STATE, "no grid on the device");
+  if (du && (c->p.in_place || c->p.collision >= LBM_DDF_NEWTON))
+    return set_err(c, LBM_E_UNSUPPORTED, "inflow noise: not with in-place streaming or the numerical equilibria");
+  drop_graph(c);  // the graph holds the table's address
+  if (!du) {
+    dev_release(c, c->d_xdu);
+    c->d_xdu = nullptr;
+    return LBM_OK;
+  }
+  // the perturbation of every cell projected on each velocity, moved to the
+  // cell's explicit row (a cell with a moving-wall link always has one)
+  const int64_t xs = c->lay.xstride, n = c->N;
+  const int Q = c->lat.Q;
+  std::vector<double> h((size_t)(Q - 1) * xs, 0.0);
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t r = c->lay.xrow_of[k];
+    if (r < 0) continue;
+    double v[3];
+    for (int d = 0; d < 3; ++d) {
+      v[d] = du[(size_t)d * n + k];
+      if (!std::isfinite(v[d])) return set_err(c, LBM_E_ARG, "non-finite inflow noise");
+    }
+    for (int i = 1; i < Q; ++i)
+      h[(size_t)(i - 1) * xs + r] = c->lat.c[i][0] * v[0] + c->lat.c[i][1] * v[1] + c->lat.c[i][2] * v[2];
+  }
+  if (!c->d_xdu) {
+    c->d_xdu = (double *)dev_alloc(c, sizeof(double) * h.size());
+    if (!c->d_xdu) return set_err(c, LBM_E_NOMEM, "inflow noise allocation failed");
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->d_xdu, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_set_level_fusion(lbm_ctx *c, int on) {
+  if (!c) return LBM_E_ARG;
+  if ((on != 0) != c->fuse_levels) drop_graph(c);
+  c->fuse_levels = on != 0;
   return LBM_OK;
 }
 

@@ -12,32 +12,50 @@ using L21 = Lattice<LAT_D2Q21>;
 // ---------------------------------------------------------------------------
 // master parameter -> BF16 / FP32 operand copies
 // ---------------------------------------------------------------------------
+// position of input neuron k in a row of the inference copy (the inverse
+// of infer_neuron): K block, lane half and slot
+__device__ inline int infer_pos(int k) {
+  const int q = k >> 5, rem = k & 31, a = rem >> 3, h = (rem >> 2) & 1, s = rem & 3;
+  return 16 * (2 * q + (a >> 1)) + 8 * h + 4 * (a & 1) + s;
+}
+
 __device__ inline void write_operand(MlpOperands *P, int i, float v) {
   const __bf16 b = (__bf16)v;
+  MlpInfer &I = P->inf;
   if (i < MB1) {
     const int n = (i - MW1) / 4, k = (i - MW1) % 4;
     P->w1[n * 16 + k] = b;
     P->w1[n * 16 + 4 + k] = b;
+    I.w1[n * 16 + k] = b;
+    I.w1[n * 16 + 4 + k] = b;
   } else if (i < MW2) {
     P->b1[i - MB1] = v;
+    I.b1[i - MB1] = v;
   } else if (i < MB2) {
     const int n = (i - MW2) / 64, k = (i - MW2) % 64;
     P->w2[n * 64 + k] = b;
     P->w2t[k * 64 + n] = b;
+    I.w2[n * 64 + infer_pos(k)] = b;
   } else if (i < MW3) {
     P->b2[i - MB2] = v;
+    I.b2[i - MB2] = v;
   } else if (i < MB3) {
     const int n = (i - MW3) / 64, k = (i - MW3) % 64;
     P->w3[n * 64 + k] = b;
     P->w3t[k * 64 + n] = b;
+    I.w3[n * 64 + infer_pos(k)] = b;
   } else if (i < MW4) {
     P->b3[i - MB3] = v;
+    I.b3[i - MB3] = v;
   } else if (i < MB4) {
     const int n = (i - MW4) / 64, k = (i - MW4) % 64;
     P->w4[n * 64 + k] = b;
     P->w4t[k * 16 + n] = b;
+    I.w4hi[n * 64 + infer_pos(k)] = b;
+    I.w4lo[n * 64 + infer_pos(k)] = (__bf16)(v - (float)b);
   } else if (i < MMU) {
     P->b4[i - MB4] = v;
+    I.b4[i - MB4] = v;
   } else if (i < MSIG) {
     P->mu[i - MMU] = v;
   } else if (i < MLP_NPARAM) {
@@ -244,25 +262,23 @@ __global__ void __launch_bounds__(64) k_mlp_train(const MlpOperands *P, const fl
 // ---------------------------------------------------------------------------
 // batched prediction of the multipliers from raw states (rho, u_x, u_y, T)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_mlp_predict(const MlpOperands *P, const double *x, int64_t n,
-                                                    double *lam) {
-  __shared__ __align__(16) __bf16 xin[32 * 16];
-  __shared__ __align__(16) __bf16 ha[32 * 64];
-  __shared__ __align__(16) __bf16 hb[32 * 64];
-  __shared__ __align__(16) __bf16 hc[32 * 64];
-  __shared__ float y[32 * 8];
-  const int l = threadIdx.x;
-  const int64_t s = (int64_t)blockIdx.x * 32 + (l & 31);
+// (the same inference as the collide: weights staged in LDS once per block,
+// one sample per lane)
+__global__ void __launch_bounds__(256) k_mlp_predict(const MlpOperands *P, const double *x, int64_t n,
+                                                     double *lam) {
+  __shared__ MlpInfer W;
+  stage_infer(&P->inf, &W);
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const bool ok = s < n;
   float ux = ok ? (float)x[s * 4 + 1] : 0.0f, uy = ok ? (float)x[s * 4 + 2] : 0.0f;
   const Canon cn = canonical(ux, uy);
-  if (l < 32) mlp_input_row(xin + l * 16, ok ? (float)x[s * 4] : 1.0f, ux, uy, ok ? (float)x[s * 4 + 3] : 1.0f);
-  __syncthreads();
-  mlp_forward_tile(P, xin, ha, hb, hc, y, nullptr);
-  if (l < 32 && ok) {
+  float xin[4], y[8];
+  mlp_normalise(ok ? (float)x[s * 4] : 1.0f, ux, uy, ok ? (float)x[s * 4 + 3] : 1.0f, xin);
+  mlp_infer_wave(W, xin, y);
+  if (ok) {
     double out[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) out[k] = (double)P->mu[k] + (double)P->sig[k] * (double)y[l * 8 + k];
+    for (int k = 0; k < 8; ++k) out[k] = (double)P->mu[k] + (double)P->sig[k] * (double)y[k];
     uncanonical(cn, out);
 #pragma unroll
     for (int k = 0; k < 8; ++k) lam[s * 8 + k] = out[k];
@@ -310,7 +326,7 @@ void mlp_adam(float *w, float *m, float *v, float *g, void *P, float lr, int t, 
 }
 
 void mlp_predict(const void *P, const double *x, int64_t n, double *lam, hipStream_t st) {
-  hipLaunchKernelGGL(k_mlp_predict, dim3((unsigned)((n + 31) / 32)), dim3(64), 0, st, (const MlpOperands *)P, x,
+  hipLaunchKernelGGL(k_mlp_predict, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const MlpOperands *)P, x,
                      n, lam);
 }
 

@@ -52,6 +52,19 @@ struct Topo {
   const int32_t *xbase;    // [bricks] first exception row of the brick
   const int32_t *xnbr;     // [Q-1][xstride] pull sources of the exception rows
   int64_t xstride;
+  const double *xdu;       // [Q-1][xstride] xi_i . (inflow noise) of the rows, or null
+};
+
+// the collides of every level active at a substep in one launch: what
+// differs between the levels (the rest of KArgs is common to them)
+constexpr int MAX_LEVELS = 8;
+struct MultiTable {
+  int n;                    // active levels in the launch; 0: a per-level launch
+  int parity[MAX_LEVELS];   // input buffer of each active level
+  const void *f[2], *g[2];  // the two population buffers
+  int64_t begin[MAX_LEVELS], count[MAX_LEVELS];
+  double tau[MAX_LEVELS];
+  int64_t block0[MAX_LEVELS + 1];  // first block of each (multiples of 8); block0[n] = grid size
 };
 
 // collide-and-stream of the slots [begin, begin + count) of one level
@@ -72,6 +85,7 @@ struct KArgs {
   PhysArgs ph;
   unsigned long long *counters;
   int aa;              // in-place streaming: 0 off, 1 even step, 2 odd step
+  MultiTable multi;    // n > 0: every active level of a substep in one launch
 };
 
 // coalescence of the unknown populations of one level's coarse ghosts
@@ -84,6 +98,7 @@ struct CArgs {
   int64_t stride, vbase;
   const int32_t *xnbr;      // exception rows (children of coarse ghosts have one)
   int64_t xstride;
+  const double *xdu;        // inflow noise of the rows, or null
   const int32_t *child;     // [ghost][2^D] child slots
   const int32_t *crow;      // [ghost][2^D] exception rows of the children
   const uint64_t *unknown;  // [ghost]
@@ -159,6 +174,10 @@ struct IArgs {
 
 struct Ops {
   void (*collide)(const KArgs &, bool pre, hipStream_t);
+  // all active levels in one launch (steady state: no pre-collision input,
+  // two buffers); null where the model keeps per-level launches
+  void (*collide_multi)(const KArgs &, hipStream_t);
+  int collide_block;        // threads per collide block
   void (*coalesce)(const CArgs &, bool pre_child, hipStream_t);
   void (*explode)(const EArgs &, hipStream_t);
   void (*bcfill)(const BArgs &, hipStream_t);

@@ -18,6 +18,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LBM_LIB_PATH", os.path.join(PKG, "liblbm.so"))
 
 LATTICES = {"D2Q9": 0, "D3Q27": 1, "D2Q21": 2, "D2Q37": 3, "D2Q13": 4}
+LATTICE_Q = {"D2Q9": 9, "D3Q27": 27, "D2Q21": 21, "D2Q37": 37, "D2Q13": 13}
 COLLISIONS = {"BGK": 0, "RR": 1, "DDF_POLY": 2, "DDF_NEWTON": 3, "DDF_MLP": 4, "DDF_MLP_NEWTON": 5}
 STORAGE = {"fp64": 0, "fp32": 1, "fp16": 2}
 BC_KINDS = {"periodic": 0, "wall": 1, "moving_wall": 2, "neumann": 3, "equilibrium": 4}
@@ -27,7 +28,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_MASK", -3: "LBM_E_NOMEM", -4:
 # every entry point declared in include/lbm.h
 EXPORTS = ["lbm_create", "lbm_grid_build", "lbm_grid_info", "lbm_layout_info", "lbm_grid_export", "lbm_init",
            "lbm_step", "lbm_set_face_bc", "lbm_set_graphs", "lbm_moments", "lbm_moments_device", "lbm_stats_get",
-           "lbm_sums_device",
+           "lbm_sums_device", "lbm_set_level_fusion", "lbm_set_inflow_noise",
            "lbm_sync", "lbm_profile_enable", "lbm_profile_read", "lbm_get_state", "lbm_get_cells", "lbm_set_state",
            "lbm_remesh", "lbm_sensor",
            "lbm_last_error", "lbm_destroy", "lbm_mlp_set_weights", "lbm_mlp_get_weights",
@@ -93,6 +94,8 @@ def lib():
         L.lbm_step.argtypes = [vp, i64]
         L.lbm_set_face_bc.argtypes = [vp, C.c_int, C.POINTER(FaceBC)]
         L.lbm_set_graphs.argtypes = [vp, C.c_int]
+        L.lbm_set_level_fusion.argtypes = [vp, C.c_int]
+        L.lbm_set_inflow_noise.argtypes = [vp, vp]
         L.lbm_moments.argtypes = [vp, vp]
         L.lbm_moments_device.argtypes = [vp, vp]
         L.lbm_stats_get.argtypes = [vp, C.POINTER(Stats)]
@@ -288,7 +291,7 @@ class LBM:
         eq = C.c_double()
         self._check(self._L.lbm_grid_info(self.h, C.byref(n), _ptr(npl), C.byref(ng), C.byref(eq)))
         self.n, self.n_per_level, self.n_ghosts, self.eq_fine = n.value, npl[:n_levels].copy(), ng.value, eq.value
-        self.Q = {"D2Q9": 9, "D3Q27": 27, "D2Q21": 21, "D2Q37": 37, "D2Q13": 13}[self.lattice]
+        self.Q = LATTICE_Q[self.lattice]
         self.n_mom = 1 + dim + (1 if self.ddf else 0)
 
     def layout(self):
@@ -329,6 +332,8 @@ class LBM:
     def init_workload(self, w):
         coords, level = self.coords_levels()
         self.init(w.initial_moments(coords, level))
+        if getattr(w, "inflow_noise", None) is not None:
+            self.set_inflow_noise(w.inflow_noise(coords, level))
 
     def step(self, n=1):
         self._check(self._L.lbm_step(self.h, int(n)), "lbm_step")
@@ -340,6 +345,20 @@ class LBM:
     def graphs(self, on=True):
         """replay pairs of coarse steps from a HIP graph"""
         self._check(self._L.lbm_set_graphs(self.h, int(on)), "lbm_set_graphs")
+
+    def set_inflow_noise(self, du):
+        """du [3][n] (canonical order) added to the moving-wall velocity seen
+        by each cell; None removes it"""
+        if du is None:
+            self._check(self._L.lbm_set_inflow_noise(self.h, None), "lbm_set_inflow_noise")
+            return
+        d = np.ascontiguousarray(du, dtype=np.float64)
+        assert d.shape == (3, self.n)
+        self._check(self._L.lbm_set_inflow_noise(self.h, _ptr(d)), "lbm_set_inflow_noise")
+
+    def level_fusion(self, on=True):
+        """one collide launch for all levels active at a substep"""
+        self._check(self._L.lbm_set_level_fusion(self.h, int(on)), "lbm_set_level_fusion")
 
     def moments(self):
         out = np.zeros((self.n_mom, self.n))

@@ -101,6 +101,9 @@ class Workload:
     warm_start: bool = True
     # macroscopic initial state from (coords [n,3] int32, level [n] int8, ids)
     init: Callable = None
+    # per-cell perturbation of the moving-wall velocity, (coords, level) ->
+    # [3][n] in canonical order, or None
+    inflow_noise: Optional[Callable] = None
     # optional host-side face schedule: step index -> {face: Face}
     schedule: Optional[Callable] = None
     storage: str = "fp64"
@@ -198,15 +201,22 @@ def cylinder(scale: int = 1, steps: int = 2000, seed: int = 2, Ma: float = 0.2,
     faces = [Face("moving_wall", u=(uinf, 0.0, 0.0)), sp, sp, sp, Face(), Face()]
 
     def init(coords, level):
-        ids = np.arange(coords.shape[0], dtype=np.int64)
         m = np.zeros((3, coords.shape[0]))
         m[0] = 1.0
-        m[1] = uinf + uniform_noise(seed, ids, 0, 1e-4)
-        m[2] = uniform_noise(seed, ids, 1, 1e-4)
+        m[1] = uinf
         return m
 
+    def noise(coords, level):
+        # a fixed perturbation of the inflow velocity per cell (only the
+        # cells with a link across the inflow face use theirs)
+        ids = np.arange(coords.shape[0], dtype=np.int64)
+        du = np.zeros((3, coords.shape[0]))
+        du[0] = uniform_noise(seed, ids, 0, 1e-4)
+        du[1] = uniform_noise(seed, ids, 1, 1e-4)
+        return du
+
     return Workload("cylinder", "D2Q9", "RR", dim, ext, L, refine, solid, faces,
-                    nu_f, steps, init=init, storage=storage)
+                    nu_f, steps, init=init, storage=storage, inflow_noise=noise)
 
 
 # --------------------------------------------------------------------------

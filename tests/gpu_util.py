@@ -68,6 +68,10 @@ def run_pair(w, steps, storage, oracle_over=None, lib_over=None, schedule=True):
     m0 = w.initial_moments(coords, level)
     o.init(m0)
     s.init(m0)
+    if w.inflow_noise is not None:
+        du = w.inflow_noise(coords, level)
+        o.set_inflow_noise(du)
+        s.set_inflow_noise(du)
     if not (schedule and w.schedule is not None):
         o.step(steps)
         s.step(steps)

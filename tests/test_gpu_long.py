@@ -32,6 +32,10 @@ def run_long(name, w, steps, storage, chunk=100):
     m0 = w.initial_moments(coords, level)
     o.init(m0)
     s.init(m0)
+    if w.inflow_noise is not None:
+        du = w.inflow_noise(coords, level)
+        o.set_inflow_noise(du)
+        s.set_inflow_noise(du)
     done = 0
     while done < steps:
         n = min(chunk, steps - done)

@@ -149,7 +149,8 @@ def test_surrogate_collision_parity(trained, variant):
     st = s3.stats()
     say(f"[mlp] airfoil/16 20 steps: Newton FP32 {e_newton}; surrogate+Newton FP32 {e_mlp}; "
         f"fallbacks {st['mlp_fallbacks']} of {sum(st['updates'])} updates")
-    assert e_mlp["u"] < 1e-4 and e_mlp["rho"] < 1e-4 and e_mlp["T"] < 1e-4
+    # the metric's bar: relative L2 <= 1e-5 against the FP64 oracle
+    assert e_mlp["u"] < 1e-5 and e_mlp["rho"] < 1e-5 and e_mlp["T"] < 1e-5
     assert st["newton_failures"] == 0
 
 
@@ -186,3 +187,81 @@ def test_surrogate_gain_over_cold_newton(trained):
         f"speed-up vs cold {t_cold / t_mlp:.2f}x, vs warm {t_warm / t_mlp:.2f}x")
     assert st_mlp["newton_iterations"] < 0.5 * st_cold["newton_iterations"]
     assert st_mlp["newton_failures"] == 0 and st_cold["newton_failures"] == 0
+
+
+def test_surrogate_alone_misses_the_constraints(trained):
+    """Variant (b), the network's multipliers used as they are: the
+    equilibrium it builds does not meet the moment constraints, so mass,
+    momentum and energy are not conserved by the collision and the run
+    drifts from the oracle.  Reported per coarse step on the scaled airfoil
+    (a closed box would be cleaner, but the airfoil is the workload): the
+    relative L2 against the oracle, the constraint residual of the network's
+    multipliers at the same states (max |G_a| / rho after one evaluation,
+    the fallback test of variant (c)), and the share of colliding states
+    outside the training box.  The bar of 1e-5 is out of reach for (b): on
+    this grid the run also leaves the representable states within a few
+    steps and latches a numeric failure (non-finite cells), as the
+    full-size airfoil does; the diagnosis uses the last finite state."""
+    w = W.airfoil(scale=16, steps=12)
+    wts = trained[0]
+    o = Oracle.from_workload(w)
+    s = B.LBM(w.lattice, "DDF_MLP", "fp32", nu_finest=w.nu_finest, T0=w.T0, gamma=w.gamma, sensor_A=w.sensor_A,
+              sensor_on=w.sensor_on, newton_tol=w.newton_tol, newton_max_it=w.newton_max_it)
+    s.grid(w.dim, w.ext, w.n_levels, w.refine, w.solid, w.faces)
+    s.mlp_set_weights(wts)
+    coords, level = s.coords_levels()
+    m0 = w.initial_moments(coords, level)
+    o.init(m0)
+    s.init(m0)
+    errs = []
+    m = s.moments()
+    failed_at = None
+    for k in range(12):
+        for face, f in w.schedule(k).items():
+            o.set_face(face, f)
+            s.set_face(face, f)
+        o.step(1)
+        s.step(1)
+        try:
+            mk = s.moments()
+        except B.LbmError as e:
+            assert e.code == -6  # the numeric latch, not another failure
+            failed_at = k
+            break
+        m = mk
+        errs.append(compare(m, o.moments(), level, 2)["rho"])
+    ok = np.isfinite(m[0])
+    x = np.stack([m[0][ok], m[1][ok], m[2][ok], m[3][ok]], axis=1)
+    speed = np.hypot(x[:, 1], x[:, 2])
+    outside = float(np.mean((x[:, 0] < 0.2) | (x[:, 0] > 5.0) | (speed > 2.5) | (x[:, 3] < 0.5) | (x[:, 3] > 3.0)))
+    # residual of the network's multipliers at the library's states
+    lam = s.mlp_predict(x)
+    xi = o.c[:, :2].astype(np.float64)
+    mv = np.stack([np.ones(len(xi)), xi[:, 0], xi[:, 1], xi[:, 0] ** 2, xi[:, 0] * xi[:, 1], xi[:, 1] ** 2,
+                   xi[:, 0] * (xi ** 2).sum(1), xi[:, 1] * (xi ** 2).sum(1)], axis=1)
+
+    def residual(st, lm):
+        # max_a |G_a| / rho of the exponential equilibrium (Eq. exponential)
+        ux, uy, T = st[1], st[2], st[3]
+        u2 = ux * ux + uy * uy
+        tgt = np.array([1.0, ux, uy, ux * ux + T, ux * uy, uy * uy + T, ux * (u2 + 4 * T), uy * (u2 + 4 * T)])
+        e = np.exp(-(1.0 + mv @ lm))
+        return float(np.max(np.abs(e @ mv - tgt)))
+
+    with np.errstate(over="ignore", invalid="ignore"):
+        res = np.array([residual(x[i], lam[i]) for i in range(0, len(x), max(1, len(x) // 400))])
+        # the same at the initial (developing, realisable) states
+        x0 = np.stack([m0[0], m0[1], m0[2], m0[3]], axis=1)
+        lam0 = s.mlp_predict(x0)
+        res0 = np.array([residual(x0[i], lam0[i]) for i in range(0, len(x0), max(1, len(x0) // 400))])
+    say(f"[mlp] variant (b) on airfoil/16: rel L2(rho) by coarse step {np.array(errs)}; non-finite cells latched "
+        f"at coarse step {failed_at}; at the last finite state: share of states outside the training box "
+        f"{outside:.3e}, network constraint residual median {np.nanmedian(res):.2e}, non-finite "
+        f"{np.mean(~np.isfinite(res)):.3f}; at the initial states median {np.median(res0):.2e}, "
+        f"max {np.max(res0):.2e}")
+    # (b) alone does not meet the bar: it diverges, or drifts beyond 1e-5
+    assert failed_at is not None or errs[-1] > 1e-5
+    # its multipliers violate the constraints (the fallback threshold of (c)
+    # is 1e-10), already at the initial states
+    assert np.median(res0) > 1e-10
+    s.close()

@@ -53,9 +53,11 @@ def test_cylinder_rr(storage, tol):
     check("cylinder/8", w, 40, storage, tol)
 
 
-@pytest.mark.parametrize("storage,tol", [("fp64", FP64_TOL), ("fp32", 1e-4), ("fp16", 3e-2)])
+@pytest.mark.parametrize("storage,tol", [("fp64", FP64_TOL), ("fp32", 1e-4), ("fp16", 1e-3)])
 def test_sphere_rr(storage, tol):
-    """three-level sphere (1/8 scale), D3Q27 RR"""
+    """three-level sphere (1/8 scale), D3Q27 RR; FP16 stores f - w_i with a
+    relative rounding of 2^-11 of |f - w_i| per store (measured u 1.3e-4,
+    worst cell 4.4e-4 after 10 coarse steps)"""
     w = W.sphere(scale=8, steps=10)
     check("sphere/8", w, 10, storage, tol)
 
@@ -127,6 +129,8 @@ def test_restart_is_bit_exact():
     f, g, lam = b.get_state()
     c = B.LBM.from_workload(w, storage="fp64")
     c.set_state(f, g, lam)
+    coords, level = c.coords_levels()
+    c.set_inflow_noise(w.inflow_noise(coords, level))  # an input, not part of the state
     c.step(6)
     assert np.array_equal(np.isnan(ma), np.isnan(c.moments()))
     mc = c.moments()
@@ -176,3 +180,21 @@ def test_graph_replay_matches_launches(name):
     sa, sb = a.stats(), b.stats()
     assert sa["updates"] == sb["updates"] and sa["coarse_steps"] == sb["coarse_steps"]
     say(f"[graph] {name}: {sb['coarse_steps']} coarse steps, graph replays identical to launches")
+
+
+def test_inflow_noise_reaches_the_flow():
+    """The cylinder's seeded inflow noise (lbm_set_inflow_noise) enters the
+    moving-wall links of the inflow cells on both sides: with it the
+    library matches the oracle to 1e-12 and differs from the run without it
+    by far more than that."""
+    w = W.cylinder(scale=16, steps=20)
+    mg, mo, level, s, o = run_pair(w, 20, "fp64")
+    assert_within(compare(mg, mo, level, w.dim), FP64_TOL)
+    w0 = W.cylinder(scale=16, steps=20)
+    w0.inflow_noise = None
+    mg0, _, _, s0, _ = run_pair(w0, 20, "fp64")
+    d = compare(mg0, mg, level, w.dim)
+    say(f"[parity] cylinder/16 with and without inflow noise: {d}")
+    assert d["u"] > 1e-8
+    s.close()
+    s0.close()
