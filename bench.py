@@ -144,9 +144,10 @@ def counted_traffic(workload_name, storage):
     return {int(k): v for k, v in rec["bytes_per_update"].items()}
 
 
-def survey_bytes_per_update(w, storage):
+def neighbour_list_bytes_per_update(w, storage):
     """algorithmic bytes one cell update moves under the neighbour-list
-    formulation of the method: read and write the Q
+    formulation of the method (V - 1 int32 neighbour links per cell, Sec. 4.4 data
+    layout; the tree-grid performance model of Sec. 6.3): read and write the Q
     populations of every distribution in the storage precision, read the
     Q - 1 int32 pull indices, and read and write the eight multipliers
     where they are kept for the warm start"""
@@ -264,14 +265,24 @@ def surrogate_leg(args):
                         "label_s": round(t1 - t0, 3), "train_s": round(t2 - t1, 3),
                         "loss_first_last": [float(hist[0]), float(hist[-1])]},
            "reference": dict(ref_stats, storage="fp64", warm_start=True)}
+    def errs(m, r):
+        return {"rho": rel_l2(m[0], r[0], vol), "u": rel_l2(m[1:3], r[1:3], vol[None, :]),
+                "T": rel_l2(m[3], r[3], vol)}
+
+    cold = None
     for name, coll, warm in [("a_cold", "DDF_NEWTON", False), ("a_warm", "DDF_NEWTON", True),
                              ("b_mlp", "DDF_MLP", True), ("c_mlp_newton", "DDF_MLP_NEWTON", True)]:
         try:
             st, m = run(coll, "fp32", warm)
             if m is not None:
-                st["rel_l2_vs_fp64"] = {"rho": rel_l2(m[0], ref[0], vol),
-                                        "u": rel_l2(m[1:3], ref[1:3], vol[None, :]),
-                                        "T": rel_l2(m[3], ref[3], vol)}
+                st["rel_l2_vs_fp64"] = errs(m, ref)
+                # against Newton at the same storage precision (cold start):
+                # what replacing the solve changes, without the FP32 rounding
+                # both share
+                if cold is None:
+                    cold = m
+                else:
+                    st["rel_l2_vs_a_cold"] = errs(m, cold)
         except B.LbmError as e:
             st = {"failed": str(e)[:160]}
         out[name] = st
@@ -332,7 +343,7 @@ def fp16_leg(w32, args):
         ups += int(s.n_per_level[l]) * n_l
     s.close()
     lay = tb / (tm * 1e-3) / 1e9 if tm > 0 else 0.0
-    sbpu = survey_bytes_per_update(w, "fp16")
+    sbpu = neighbour_list_bytes_per_update(w, "fp16")
     ach = sbpu * ups / (tm * 1e-3) / 1e9 if tm > 0 else 0.0
     return {"value": round(per_step * args.steps / dt / 1e6, 2), "unit": "MLUPS",
             "ms_per_step": round(dt / args.steps * 1e3, 4),
@@ -385,6 +396,8 @@ def main():
                     help="coarse steps before the timed ones: the Mach ramp ends at 200")
     ap.add_argument("--sur-samples", type=int, default=3_300_000)
     ap.add_argument("--sur-epochs", type=int, default=40)
+    ap.add_argument("--surrogate-only", action="store_true",
+                    help="run only the surrogate leg and print its JSON object")
     ap.add_argument("--cpu-baseline-child", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="one plain 1 GiB device-to-device copy, to scale the HBM byte counters")
@@ -394,6 +407,9 @@ def main():
         return
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.surrogate_only:
+        print(json.dumps({"surrogate": surrogate_leg(args)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -466,7 +482,7 @@ def main():
     n_upd = sum(int(s.n_per_level[l]) * s.profile_read(l)[0] for l in range(L))
     # achieved: the method's algorithmic bytes (neighbour-list formulation)
     # per update x the updates of the timed launches / their summed duration
-    sbpu = survey_bytes_per_update(w, storage)
+    sbpu = neighbour_list_bytes_per_update(w, storage)
     achieved = sbpu * n_upd / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
     _, _, bpu_f = s.profile_read(L - 1)
     # counter-measured HBM bytes of the same launches, at the same rate basis
@@ -525,7 +541,7 @@ def main():
             times.append((time.perf_counter() - t0) * 1e3)
             s.step(1)
         out["remesh"] = {"ms": [round(t, 1) for t in times], "cells_after": int(s.n),
-                         "note": "tree built on the host, state moved on the device"}
+                         "note": "tree, layout and source lists built on the device, state moved on the device"}
     s.close()
     if args.workload == "sphere" and storage == "fp32" and not args.no_fp16:
         out["fp16_storage"] = fp16_leg(w, args)

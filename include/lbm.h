@@ -158,6 +158,17 @@ lbm_status lbm_grid_build(lbm_ctx *ctx, int dim, const int32_t ext_coarse[3],
                           int n_levels, const lbm_mask *refine,
                           const lbm_mask *solid, const lbm_face_bc faces[6]);
 
+/* Where lbm_grid_build and lbm_remesh construct the tree and its brick
+ * layout (Secs. 4.3-4.4; Sec. 8 names the host-side tree construction as
+ * the cost of remeshing): on = 1 (the default) builds them on the GPU,
+ * every rule of the construction applied per cell in parallel (Z order by
+ * a radix sort of Morton keys, lists by prefix sums), and copies the result
+ * into the context's host copy; on = 0 builds them on the host.  Both give
+ * the same grid value for value and the same errors.  Host-only contexts
+ * always build on the host.  Takes effect at the next build.  Errors:
+ * LBM_E_ARG (null context). */
+lbm_status lbm_set_device_build(lbm_ctx *ctx, int on);
+
 /* Cell counts; n_per_level has n_levels entries.  eq_fine_cells is
  * sum_l n_l / 2^(L-1-l) (Sec. 7.5, "equivalent fine cells").  Any output
  * pointer may be NULL. */
@@ -175,6 +186,18 @@ lbm_status lbm_grid_info(lbm_ctx *ctx, int64_t *n_cells, int64_t *n_per_level,
  * rows_per_level have n_levels entries.  Any output pointer may be NULL. */
 lbm_status lbm_layout_info(lbm_ctx *ctx, int64_t *n_slots, int64_t *n_exception_rows,
                            int64_t *slots_per_level, int64_t *rows_per_level);
+
+/* The brick layout of the grid (Sec. 4.4 data layout, as placed for the
+ * device), for inspection and tests: slot_of [n_cells] the slot of each
+ * canonical cell; xrow_of [n_cells] its exception row or -1; nbrick
+ * [n_slots / 64][nbp] the neighbour brick ids (nbp = 16 in 2-D, 32 in 3-D;
+ * -1 where there is none); xmask [n_slots / 64] the lanes with exception
+ * rows; xnbr [Q-1][n_rows] the pull sources of the exception rows (slot,
+ * coalesced slot >= n_slots, -1 bounce-back, -2 - k moving wall of face k).
+ * Sizes from lbm_layout_info; any pointer may be NULL.  Errors: LBM_E_ARG,
+ * LBM_E_STATE (no grid). */
+lbm_status lbm_layout_export(lbm_ctx *ctx, int32_t *slot_of, int32_t *xrow_of, int32_t *nbrick, uint64_t *xmask,
+                             int32_t *xnbr);
 
 /* Export the tables in canonical form (any pointer may be NULL):
  * coords [n][3], level [n], flags [n], nbr [n][Q-1] (sentinels above),

@@ -15,7 +15,8 @@ LIB = os.path.join(PKG, "liblbm.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HIP_SOURCES = ["k_d2q9.hip", "k_d3q27.hip", "k_d2q13.hip", "k_d2q21.hip", "k_d2q37.hip", "k_d2q37_newton64.hip",
-               "k_d2q37_newton32.hip", "mlp.hip", "k_remesh.hip", "sums.hip"]
+               "k_d2q37_newton32.hip", "mlp.hip", "k_remesh.hip", "sums.hip",
+               "grid_device.hip"]
 CXX_SOURCES = ["grid_builder.cpp", "layout.cpp", "remesh.cpp", "lbm_api.cpp"]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

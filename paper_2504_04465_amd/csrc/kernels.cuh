@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "grid_builder.h"
 #include "lattice.h"
@@ -40,16 +41,20 @@ struct Sto<double> {
   using C = double;
   __device__ static C ld(const double *p, int64_t k, double) { return p[k]; }
   __device__ static C ldv(double v, double) { return v; }
+  __device__ static C ldr(double v) { return v; }
   __device__ static void st(double *p, int64_t k, C v, double) { p[k] = v; }
   __device__ static void stn(double *p, int64_t k, C v, double) { __builtin_nontemporal_store(v, p + k); }
+  __device__ static void stp(double *p, C v, double) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct Sto<float> {
   using C = float;
   __device__ static C ld(const float *p, int64_t k, double) { return p[k]; }
   __device__ static C ldv(float v, double) { return v; }
+  __device__ static C ldr(float v) { return v; }
   __device__ static void st(float *p, int64_t k, C v, double) { p[k] = v; }
   __device__ static void stn(float *p, int64_t k, C v, double) { __builtin_nontemporal_store(v, p + k); }
+  __device__ static void stp(float *p, C v, double) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct Sto<__half> {
@@ -58,11 +63,23 @@ struct Sto<__half> {
     return __half2float(p[k]) + (float)w;
   }
   __device__ static C ldv(__half v, double w) { return __half2float(v) + (float)w; }
-  __device__ static void st(__half *p, int64_t k, C v, double w) {
-    p[k] = __float2half_rn(v - (float)w);
+  // the stored value itself (f_i - w_i), for kernels that work on it
+  __device__ static C ldr(__half v) { return __half2float(v); }
+  // the FP32 value is rounded to FP32 before the conversion: left to
+  // itself the compiler fuses the last multiply or add into a mixed-precision
+  // FMA with one rounding to FP16 in some kernels and not in others, and
+  // kernels that must agree bit for bit (in place vs two buffers) would not
+  __device__ static __half cvt(C v, double w) {
+    float t = v - (float)w;
+    asm volatile("" : "+v"(t));
+    return __float2half_rn(t);
   }
+  __device__ static void st(__half *p, int64_t k, C v, double w) { p[k] = cvt(v, w); }
   __device__ static void stn(__half *p, int64_t k, C v, double w) {
-    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v - (float)w)), (unsigned short *)p + k);
+    __builtin_nontemporal_store(__half_as_ushort(cvt(v, w)), (unsigned short *)p + k);
+  }
+  __device__ static void stp(__half *p, C v, double w) {
+    __builtin_nontemporal_store(__half_as_ushort(cvt(v, w)), (unsigned short *)p);
   }
 };
 
@@ -154,7 +171,10 @@ __device__ inline int lane_bits(int p, int d) {
 // AA = 2: the single in-place buffer after an even step holds cell x's
 // post-collision population i in row opp(i); pulls swap the rows (a wall
 // returns the cell's own row i).
-template <class L, class S, bool PRE, bool DDF, int AA = 0, bool NZ = true>
+//
+// RAW: FP16 storage only, the populations are returned as stored (f_i - w_i);
+// the moving-wall term is the same in that representation.
+template <class L, class S, bool PRE, bool DDF, int AA = 0, bool NZ = true, bool RAW = false>
 __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnbr, int64_t xstride, int64_t row,
                                   int64_t stride, int64_t vbase, int64_t c, const double (&uw)[6][3], double cs2w,
                                   typename Sto<S>::C *f, typename Sto<S>::C *g, uint64_t want = ~0ull,
@@ -172,7 +192,7 @@ __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnb
     if (PRE) idx = (int64_t)i * stride + ((int64_t)s >= vbase ? (int64_t)s : c);
     else idx = s >= 0 ? (int64_t)ri * stride + s : (int64_t)ro * stride + c;
     // the lattice is symmetric: w of the opposite population is w_i
-    f[i] = Sto<S>::ld(fin, idx, L::S.w[i]);
+    f[i] = RAW ? Sto<S>::ldr(fin[idx]) : Sto<S>::ld(fin, idx, L::S.w[i]);
     if (DDF) g[i] = Sto<S>::ld(gin, idx, 0.0);
   }
   if (!PRE) {
@@ -197,20 +217,20 @@ __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnb
 //
 // Lanes flagged in the brick's exception mask read their explicit row:
 // every source is loaded before any is used, so the loads overlap.
-template <class L, class S, bool PRE, bool DDF, int AA = 0, bool NZ = true>
+template <class L, class S, bool PRE, bool DDF, int AA = 0, bool NZ = true, bool RAW = false>
 __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const uint32_t *nbs, int64_t stride,
                               int64_t vbase, int64_t c, int lane, int32_t brick, uint64_t xm,
                               const double (&uw)[6][3], double cs2w, typename Sto<S>::C *f,
                               typename Sto<S>::C *g) {
   using C = typename Sto<S>::C;
   constexpr int BS = Brick<L>::BS, R = L::B, D = L::D;
-  f[0] = Sto<S>::ld(fin, c, L::S.w[0]);
+  f[0] = RAW ? Sto<S>::ldr(fin[c]) : Sto<S>::ld(fin, c, L::S.w[0]);
   if (DDF) g[0] = Sto<S>::ld(gin, c, 0.0);
   if (!((xm >> lane) & 1ull)) {
     if (PRE) {
 #pragma unroll
       for (int i = 1; i < L::Q; ++i) {
-        f[i] = Sto<S>::ld(fin, (int64_t)i * stride + c, L::S.w[i]);
+        f[i] = RAW ? Sto<S>::ldr(fin[(int64_t)i * stride + c]) : Sto<S>::ld(fin, (int64_t)i * stride + c, L::S.w[i]);
         if (DDF) g[i] = Sto<S>::ld(gin, (int64_t)i * stride + c, 0.0);
       }
       return;
@@ -239,13 +259,14 @@ __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const 
       const uint32_t k = K[0][cx_<L>(i, 0) + R] + K[1][cx_<L>(i, 1) + R] + K[2][cx_<L>(i, 2) + R];
       const uint32_t off = nbs[k >> 18] + (k & 0xffffu);
       const int64_t ri = AA == 2 ? L::S.opp[i] : i;
-      f[i] = Sto<S>::ldv(*(const S *)(fb + ri * pstride + off), L::S.w[i]);
+      const S v = *(const S *)(fb + ri * pstride + off);
+      f[i] = RAW ? Sto<S>::ldr(v) : Sto<S>::ldv(v, L::S.w[i]);
       if (DDF) g[i] = Sto<S>::ldv(*(const S *)(gb + ri * pstride + off), 0.0);
     }
   } else {
     const int64_t row = tp.xbase[brick] + __popcll(xm & ((1ull << lane) - 1ull));
-    gather_row<L, S, PRE, DDF, AA, NZ>(fin, gin, tp.xnbr, tp.xstride, row, stride, vbase, c, uw, cs2w, f, g, ~0ull,
-                                       tp.xdu);
+    gather_row<L, S, PRE, DDF, AA, NZ, RAW>(fin, gin, tp.xnbr, tp.xstride, row, stride, vbase, c, uw, cs2w, f, g,
+                                            ~0ull, tp.xdu);
   }
 }
 
@@ -253,13 +274,14 @@ __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const 
 // to row i of x + xi_i (the cell whose pull of i reads x), or, where that is a
 // wall, back to the cell's own row opp(i) with the moving-wall correction of
 // population opp(i) (the bounce-back the next pull would have applied).
-template <class L, class S, bool DDF>
+// RAW: f holds f_i - w_i (FP16 storage), stored as it is.
+template <class L, class S, bool DDF, bool RAW = false>
 __device__ inline void push_store(S *fout, S *gout, const Topo &tp, const uint32_t *nbs, int64_t stride, int64_t c,
                                   int lane, int32_t brick, uint64_t xm, const double (&uw)[6][3], double cs2w,
                                   const typename Sto<S>::C *f, const typename Sto<S>::C *g) {
   using C = typename Sto<S>::C;
   constexpr int BS = Brick<L>::BS, R = L::B, D = L::D;
-  Sto<S>::stn(fout, c, f[0], L::S.w[0]);
+  Sto<S>::stn(fout, c, f[0], RAW ? 0.0 : L::S.w[0]);
   if (DDF) Sto<S>::stn(gout, c, g[0], 0.0);
   if (!((xm >> lane) & 1ull)) {
     uint32_t K[3][2 * R + 1];
@@ -287,7 +309,7 @@ __device__ inline void push_store(S *fout, S *gout, const Topo &tp, const uint32
       const int j = L::S.opp[i];
       const uint32_t k = K[0][cx_<L>(j, 0) + R] + K[1][cx_<L>(j, 1) + R] + K[2][cx_<L>(j, 2) + R];
       const uint32_t off = nbs[k >> 18] + (k & 0xffffu);
-      Sto<S>::stn((S *)(fb + i * pstride + off), 0, f[i], L::S.w[i]);
+      Sto<S>::stn((S *)(fb + i * pstride + off), 0, f[i], RAW ? 0.0 : L::S.w[i]);
       if (DDF) Sto<S>::stn((S *)(gb + i * pstride + off), 0, g[i], 0.0);
     }
   } else {
@@ -296,14 +318,22 @@ __device__ inline void push_store(S *fout, S *gout, const Topo &tp, const uint32
     for (int i = 1; i < L::Q; ++i) {
       const int j = L::S.opp[i];
       const int32_t s = tp.xnbr[(int64_t)(j - 1) * tp.xstride + row];
+      // a population the cell pulls from itself (a fine ghost at the edge of
+      // its level keeps it) is stored in its own row; nobody pulls from a
+      // cell's own slot through the opposite link, so that push is dropped
+      if (tp.xnbr[(int64_t)(i - 1) * tp.xstride + row] == (int32_t)c) {
+        Sto<S>::stn(fout, (int64_t)i * stride + c, f[i], RAW ? 0.0 : L::S.w[i]);
+        if (DDF) Sto<S>::stn(gout, (int64_t)i * stride + c, g[i], 0.0);
+      }
+      if (s == (int32_t)c) continue;
       if (s >= 0) {
-        Sto<S>::stn(fout, (int64_t)i * stride + s, f[i], L::S.w[i]);
+        Sto<S>::stn(fout, (int64_t)i * stride + s, f[i], RAW ? 0.0 : L::S.w[i]);
         if (DDF) Sto<S>::stn(gout, (int64_t)i * stride + s, g[i], 0.0);
       } else {
         C v = f[i];
         if (s <= -2)
           v += (C)(2.0 * L::S.w[j] * wall_dot<L>(uw, -2 - s, j) / cs2w);  // no inflow noise in place
-        Sto<S>::stn(fout, (int64_t)j * stride + c, v, L::S.w[j]);
+        Sto<S>::stn(fout, (int64_t)j * stride + c, v, RAW ? 0.0 : L::S.w[j]);
         if (DDF) Sto<S>::stn(gout, (int64_t)j * stride + c, g[i], 0.0);
       }
     }
@@ -396,9 +426,15 @@ __device__ inline C upow(C x, int e) {
 // f*_i = w_i sum_m H_m(xi_i) a*_m / (m! cs2^|m|), a*_m = a_eq,m + k a_neq,m,
 // with a_neq,m the closed pair sum that solves the non-equilibrium
 // recursion; evaluated by sum factorisation one axis at a time.
-template <class L, class C>
+//
+// SH: the shifted representation h_i = f_i - w_i on both sides.  P is then
+// sum xi_a xi_b h_i (the lattice's own cs2 delta_ab left out), rho1 = rho - 1
+// and rhop1 = rhop - 1 are passed as computed from the h_i, and f receives
+// h*_i = f*_i - w_i: the zeroth coefficient is a*_0 - 1, every other term is
+// unchanged.  No cancellation against 1 or cs2 happens in FP32.
+template <class L, class C, bool SH = false>
 __device__ inline void rr_product(C *f, C rho, C rhop, const C *u, C (&P)[3][3], C k,
-                                  bool trace_eq) {
+                                  bool trace_eq, C rho1 = (C)0, C rhop1 = (C)0) {
   constexpr int D = L::D;
   constexpr C cs2 = (C)L::cs2, ics2 = (C)(1.0 / L::cs2);
   C A[3][3];
@@ -406,7 +442,7 @@ __device__ inline void rr_product(C *f, C rho, C rhop, const C *u, C (&P)[3][3],
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b)
-      A[a][b] = (a < D && b < D) ? P[a][b] - rho * u[a] * u[b] - (a == b ? rho * cs2 : (C)0) : (C)0;
+      A[a][b] = (a < D && b < D) ? P[a][b] - rho * u[a] * u[b] - (a == b ? (SH ? rho1 : rho) * cs2 : (C)0) : (C)0;
   if (trace_eq) {
     C tr = (C)0;
 #pragma unroll
@@ -452,6 +488,7 @@ __device__ inline void rr_product(C *f, C rho, C rhop, const C *u, C (&P)[3][3],
 #pragma unroll
         for (int d = 0; d < 3; ++d) scale *= (m[d] == 2 ? (C)0.5 * ics2 * ics2 : (m[d] == 1 ? ics2 : (C)1));
         b[mx][my][mz] = (aeq + k * an) * scale;
+        if (SH && mx == 0 && my == 0 && mz == 0) b[0][0][0] = rhop1;
       }
   // h_0 = 1, h_1 = xi, h_2 = xi^2 - cs2 evaluated at xi in {-1, 0, 1}
   C T1[3][3][3];
@@ -946,6 +983,25 @@ __device__ inline void cell_moments(const C *f, const C *g, C Cv, C &rho, C (&u)
   T = DDF ? (e2 + gs - rho * uu) / ((C)2 * rho * Cv) : (C)0;
 }
 
+// the same from h_i = f_i - w_i (single distribution): rho1 = sum h_i is
+// rho - 1 without rounding against 1; sum w_i xi_i = 0 leaves j unchanged
+template <class L, class C>
+__device__ inline void cell_moments_shifted(const C *h, C &rho1, C &rho, C (&u)[3]) {
+  rho1 = (C)0;
+  C j[3] = {(C)0, (C)0, (C)0};
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    rho1 += h[i];
+#pragma unroll
+    for (int d = 0; d < L::D; ++d)
+      if (cx_<L>(i, d) != 0) j[d] += (C)cx_<L>(i, d) * h[i];
+  }
+  rho = (C)1 + rho1;
+  const C inv = (C)1 / rho;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) u[d] = d < L::D ? j[d] * inv : (C)0;
+}
+
 // equilibrium of any model at a macroscopic state; Newton family updates lam
 template <class L, int COLL, class C>
 __device__ inline int equilibrium_any(C rho, const C *u, C T, const PhysArgs &ph, double *lam,
@@ -1041,7 +1097,7 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
   int64_t blk, begin = a.begin, count = a.count;
   const void *fin_p = a.fin, *gin_p = a.gin;
   void *fout_p = a.fout, *gout_p = a.gout;
-  double tau = a.ph.tau;
+  double tau = a.ph.tau, omega = a.ph.omega, krr = a.ph.krr;
   bool multi = false;
   if constexpr (!PRE && AA == 0 && COLL < COLL_DDF_NEWTON) multi = a.multi.n > 0;
   if (multi) {
@@ -1054,6 +1110,8 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
     begin = a.multi.begin[k];
     count = a.multi.count[k];
     tau = a.multi.tau[k];
+    omega = a.multi.omega[k];
+    krr = a.multi.krr[k];
     const int p = a.multi.parity[k];
     fin_p = a.multi.f[p];
     fout_p = (void *)a.multi.f[1 - p];
@@ -1075,23 +1133,30 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
   const S *gin = (const S *)gin_p;
   C f[Q];
   C g[DDF ? Q : 1];
-  gather<L, S, PRE || AA == 1, DDF, AA == 2 ? 2 : 0, NZ>(fin, gin, a.topo, nbs[threadIdx.x >> 6], stride, a.vbase, c,
-                                                   threadIdx.x & 63, brick, a.topo.xmask[brick], a.ph.uw,
-                                                   a.ph.cs2w, f, g);
+  // FP16 storage with recursive regularisation on a product lattice works on
+  // the stored h_i = f_i - w_i throughout: no shift on the way in or out,
+  // and the moments and the regularised populations are formed from the
+  // small deviations instead of from f_i ~ w_i
+  constexpr bool SH = std::is_same<S, __half>::value && COLL == COLL_RR && product_basis<L>();
+  gather<L, S, PRE || AA == 1, DDF, AA == 2 ? 2 : 0, NZ, SH>(fin, gin, a.topo, nbs[threadIdx.x >> 6], stride,
+                                                       a.vbase, c, threadIdx.x & 63, brick, a.topo.xmask[brick],
+                                                       a.ph.uw, a.ph.cs2w, f, g);
   if (!(fl & (F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ))) {
-    C rho, u[3], T;
-    cell_moments<L, C, DDF>(f, g, (C)a.ph.Cv, rho, u, T);
-    C rhop = rho;
+    C rho, u[3], T = (C)0, rho1 = (C)0;
+    if constexpr (SH) cell_moments_shifted<L, C>(f, rho1, rho, u);
+    else cell_moments<L, C, DDF>(f, g, (C)a.ph.Cv, rho, u, T);
+    C rhop = rho, rhop1 = rho1;
     if (fl & F_SPONGE) {
       const C s = (C)a.sigma[c];
       rhop = rho * ((C)1 - s) + s * (C)a.rho_inf[c];
+      if constexpr (SH) rhop1 = rho1 * ((C)1 - s) + s * ((C)a.rho_inf[c] - (C)1);
     }
     if (!(rho > (C)0) || !isfinite(rho)) count_add(a.counters, CNT_NONFINITE, 1);
     if constexpr (COLL == COLL_BGK) {
       C feq[Q];
       if constexpr (product_basis<L>()) equilibrium_product<L, C>(rhop, u, feq);
       else equilibrium_hermite3<L, C>(rhop, u, feq);
-      const C om = (C)(1.0 / tau);
+      const C om = (C)omega;
 #pragma unroll
       for (int i = 0; i < Q; ++i) f[i] = f[i] - om * (f[i] - feq[i]);
     } else if constexpr (COLL == COLL_RR) {
@@ -1114,9 +1179,9 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
 #pragma unroll
         for (int y = 0; y < x; ++y) P[x][y] = P[y][x];
       if constexpr (product_basis<L>())
-        rr_product<L, C>(f, rho, rhop, u, P, (C)(1.0 - 1.0 / tau), a.ph.trace_eq != 0);
+        rr_product<L, C, SH>(f, rho, rhop, u, P, (C)krr, a.ph.trace_eq != 0, rho1, rhop1);
       else
-        rr_hermite3<L, C>(f, rho, rhop, u, P, (C)(1.0 - 1.0 / tau), a.ph.trace_eq != 0);
+        rr_hermite3<L, C>(f, rho, rhop, u, P, (C)krr, a.ph.trace_eq != 0);
     } else {
       C feq[Q], geq[Q];
       double lam[NLAM];
@@ -1166,15 +1231,36 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
   }
   S *fout = (S *)fout_p;
   S *gout = (S *)gout_p;
+  if constexpr (AA != 0) {
+    // in place on a refined grid, a coarse ghost also leaves its
+    // post-collision populations in its coalesced slot, row i, for the
+    // explosion (pushed to the neighbours they are scattered)
+    if (a.gslot) {
+      const int32_t vs = a.gslot[c];
+      if (vs >= 0) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          Sto<S>::stn(fout, (int64_t)i * stride + vs, f[i], SH ? 0.0 : L::S.w[i]);
+          if (DDF) Sto<S>::stn(gout, (int64_t)i * stride + vs, g[i], 0.0);
+        }
+      }
+    }
+  }
   if constexpr (AA == 2) {
-    push_store<L, S, DDF>(fout, gout, a.topo, nbs[threadIdx.x >> 6], stride, c, threadIdx.x & 63, brick,
+    push_store<L, S, DDF, SH>(fout, gout, a.topo, nbs[threadIdx.x >> 6], stride, c, threadIdx.x & 63, brick,
                           a.topo.xmask[brick], a.ph.uw, a.ph.cs2w, f, g);
   } else {
+    // row base (uniform) + the cell's 32-bit byte offset: the address needs
+    // no per-lane 64-bit arithmetic (slots x bytes < 2^32 on every grid)
+    char *ob = (char *)fout;
+    char *gb = (char *)gout;
+    const int64_t pstride = stride * (int64_t)sizeof(S);
+    const uint32_t co = (uint32_t)c * (uint32_t)sizeof(S);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int64_t r = AA == 1 ? L::S.opp[i] : i;
-      Sto<S>::stn(fout, r * stride + c, f[i], L::S.w[i]);
-      if (DDF) Sto<S>::stn(gout, r * stride + c, g[i], 0.0);
+      Sto<S>::stp((S *)(ob + r * pstride + co), f[i], SH ? 0.0 : L::S.w[i]);
+      if (DDF) Sto<S>::stp((S *)(gb + r * pstride + co), g[i], 0.0);
     }
   }
 }
@@ -1184,7 +1270,10 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
 // each lane pulls the child's population as the fine level's next update
 // would, the lanes of a ghost are summed with wavefront shuffles
 // ---------------------------------------------------------------------------
-template <class L, class S, bool PRE, bool DDF, bool LAM>
+// In place (AAF = 2: the fine level at an odd phase, its rows swapped) the
+// children are read as that level's swapped pull; SW: the coarse level is at
+// an odd phase and reads population i of its coalesced slot from row opp(i).
+template <class L, class S, bool PRE, bool DDF, bool LAM, int AAF = 0, bool SW = false>
 __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
   using C = typename Sto<S>::C;
   constexpr int NCH = 1 << L::D;
@@ -1223,8 +1312,9 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
       if (need && ch >= 0) {
         const int32_t sv = a.xnbr[(int64_t)(i - 1) * a.xstride + crow];
         int64_t idx;
+        const int64_t ri = AAF == 2 ? L::S.opp[i] : i, ro = AAF == 2 ? i : L::S.opp[i];
         if (PRE) idx = (int64_t)i * a.stride + ((int64_t)sv >= a.vbase ? (int64_t)sv : (int64_t)ch);
-        else idx = sv >= 0 ? (int64_t)i * a.stride + sv : (int64_t)L::S.opp[i] * a.stride + ch;
+        else idx = sv >= 0 ? ri * a.stride + sv : ro * a.stride + ch;
         v = Sto<S>::ld(fin, idx, L::S.w[i]);
         if (DDF) vg = Sto<S>::ld(gin, idx, 0.0);
         if (!PRE && sv <= -2)
@@ -1234,8 +1324,9 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
       v = group_sum<NCH, C>(v);
       if (DDF) vg = group_sum<NCH, C>(vg);
       if (lead && need) {
-        Sto<S>::st(fout, (int64_t)i * a.stride + slot, v / nf, L::S.w[i]);
-        if (DDF) Sto<S>::st(gout, (int64_t)i * a.stride + slot, vg / nf, 0.0);
+        const int64_t r = SW ? L::S.opp[i] : i;
+        Sto<S>::st(fout, r * a.stride + slot, v / nf, L::S.w[i]);
+        if (DDF) Sto<S>::st(gout, r * a.stride + slot, vg / nf, 0.0);
       }
     }
   } else {
@@ -1243,8 +1334,8 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
     // (every child of a coarse ghost has an explicit row), all loads first
     C f[L::Q], g[DDF ? L::Q : 1];
     if (ch >= 0)
-      gather_row<L, S, PRE, DDF>(fin, gin, a.xnbr, a.xstride, crow, a.stride, a.vbase, ch, a.uw, a.cs2w, f, g, mask,
-                                 a.xdu);
+      gather_row<L, S, PRE, DDF, AAF>(fin, gin, a.xnbr, a.xstride, crow, a.stride, a.vbase, ch, a.uw, a.cs2w, f, g,
+                                      mask, a.xdu);
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
       const bool need = (mask >> i) & 1ull;
@@ -1253,8 +1344,9 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
       v = group_sum<NCH, C>(v);
       if (DDF) vg = group_sum<NCH, C>(vg);
       if (lead && need) {
-        Sto<S>::st(fout, (int64_t)i * a.stride + slot, v / nf, L::S.w[i]);
-        if (DDF) Sto<S>::st(gout, (int64_t)i * a.stride + slot, vg / nf, 0.0);
+        const int64_t r = SW ? L::S.opp[i] : i;
+        Sto<S>::st(fout, r * a.stride + slot, v / nf, L::S.w[i]);
+        if (DDF) Sto<S>::st(gout, r * a.stride + slot, vg / nf, 0.0);
       }
     }
   }
@@ -1272,9 +1364,17 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
 }
 
 // uniform explosion (Eq. explosion_uniform): children take every
-// post-collision population of their coarse ghost (raw copy of storage)
-template <class L, class S, bool DDF, bool LAM>
+// post-collision population of their coarse ghost (raw copy of storage).
+// MODE 0: two buffers, from the ghost's slot into the child's rows.  In
+// place the ghost's populations are read from its coalesced slot, where its
+// collide left them; MODE 1 (fine level at an odd phase): child row opp(i)
+// takes population i; MODE 2 (even phase): population i goes to row i of
+// the cell that pulls it from the child, as the child's own push would have
+// sent it (a wall returns it to the child's row opp(i) with the moving-wall
+// term; a population the child pulls from itself stays in its row i).
+template <class L, class S, bool DDF, bool LAM, int MODE = 0>
 __global__ void __launch_bounds__(BLOCK) k_explode(const EArgs a) {
+  using C = typename Sto<S>::C;
   constexpr int NCH = 1 << L::D;
   const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int64_t gl = t / NCH;
@@ -1283,19 +1383,46 @@ __global__ void __launch_bounds__(BLOCK) k_explode(const EArgs a) {
   const int32_t ch = a.child[gk * NCH + (t % NCH)];
   if (ch < 0) return;
   const int64_t G = a.ghost_cell[gk];
+  const int64_t src = MODE == 0 ? G : a.vbase + gk;
   const S *fin = (const S *)a.fin_coarse;
   S *fout = (S *)a.fout_fine;
   S v[L::Q], vg[DDF ? L::Q : 1];
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) v[i] = fin[(int64_t)i * a.stride + G];
+  for (int i = 0; i < L::Q; ++i) v[i] = fin[(int64_t)i * a.stride + src];
   if (DDF)
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) vg[i] = ((const S *)a.gin_coarse)[(int64_t)i * a.stride + G];
+    for (int i = 0; i < L::Q; ++i) vg[i] = ((const S *)a.gin_coarse)[(int64_t)i * a.stride + src];
+  S *gout = (S *)a.gout_fine;
+  if constexpr (MODE == 2) {
+    const int64_t crow = a.crow[gk * NCH + (t % NCH)];
+    fout[ch] = v[0];
+    if (DDF) gout[ch] = vg[0];
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) fout[(int64_t)i * a.stride + ch] = v[i];
-  if (DDF)
+    for (int i = 1; i < L::Q; ++i) {
+      const int j = L::S.opp[i];
+      if (a.xnbr[(int64_t)(i - 1) * a.xstride + crow] == ch) {
+        fout[(int64_t)i * a.stride + ch] = v[i];
+        if (DDF) gout[(int64_t)i * a.stride + ch] = vg[i];
+      }
+      const int32_t s = a.xnbr[(int64_t)(j - 1) * a.xstride + crow];
+      if (s == ch) continue;
+      if (s >= 0) {
+        fout[(int64_t)i * a.stride + s] = v[i];
+        if (DDF) gout[(int64_t)i * a.stride + s] = vg[i];
+      } else {
+        C w = Sto<S>::ldv(v[i], L::S.w[i]);
+        if (s <= -2) w += (C)(2.0 * L::S.w[j] * wall_dot<L>(a.uw, -2 - s, j) / a.cs2w);
+        Sto<S>::st(fout, (int64_t)j * a.stride + ch, w, L::S.w[j]);
+        if (DDF) gout[(int64_t)j * a.stride + ch] = vg[i];
+      }
+    }
+  } else {
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) ((S *)a.gout_fine)[(int64_t)i * a.stride + ch] = vg[i];
+    for (int i = 0; i < L::Q; ++i) fout[(int64_t)(MODE == 1 ? L::S.opp[i] : i) * a.stride + ch] = v[i];
+    if (DDF)
+#pragma unroll
+      for (int i = 0; i < L::Q; ++i) gout[(int64_t)(MODE == 1 ? L::S.opp[i] : i) * a.stride + ch] = vg[i];
+  }
   if (LAM)
 #pragma unroll
     for (int k = 0; k < NLAM; ++k) ((LamT<S> *)a.lam)[(int64_t)k * a.stride + ch] = ((LamT<S> *)a.lam)[(int64_t)k * a.stride + G];
@@ -1638,12 +1765,26 @@ struct Launch {
     const int64_t lanes = a.count << L::D;
     a.ngrp = (int)std::min<int64_t>(8, std::max<int64_t>(1, (256 * BLOCK) / lanes));
     const int64_t work = lanes * a.ngrp;
-    if (pre) hipLaunchKernelGGL((k_coalesce<L, S, true, DDF, LAM>), dim3(nblocks(work)), dim3(BLOCK), 0, s, a);
-    else hipLaunchKernelGGL((k_coalesce<L, S, false, DDF, LAM>), dim3(nblocks(work)), dim3(BLOCK), 0, s, a);
+    const dim3 nb(nblocks(work));
+    if (a.swap) {
+      // in place, coarse level at an odd phase
+      if (a.aa == 2) hipLaunchKernelGGL((k_coalesce<L, S, false, DDF, LAM, 2, true>), nb, dim3(BLOCK), 0, s, a);
+      else if (pre) hipLaunchKernelGGL((k_coalesce<L, S, true, DDF, LAM, 0, true>), nb, dim3(BLOCK), 0, s, a);
+      else hipLaunchKernelGGL((k_coalesce<L, S, false, DDF, LAM, 0, true>), nb, dim3(BLOCK), 0, s, a);
+    } else if (a.aa == 2) {
+      hipLaunchKernelGGL((k_coalesce<L, S, false, DDF, LAM, 2>), nb, dim3(BLOCK), 0, s, a);
+    } else if (pre) {
+      hipLaunchKernelGGL((k_coalesce<L, S, true, DDF, LAM>), nb, dim3(BLOCK), 0, s, a);
+    } else {
+      hipLaunchKernelGGL((k_coalesce<L, S, false, DDF, LAM>), nb, dim3(BLOCK), 0, s, a);
+    }
   }
   static void explode(const EArgs &a, hipStream_t s) {
     if (a.count <= 0) return;
-    hipLaunchKernelGGL((k_explode<L, S, DDF, LAM>), dim3(nblocks(a.count << L::D)), dim3(BLOCK), 0, s, a);
+    const dim3 nb(nblocks(a.count << L::D));
+    if (a.mode == 1) hipLaunchKernelGGL((k_explode<L, S, DDF, LAM, 1>), nb, dim3(BLOCK), 0, s, a);
+    else if (a.mode == 2) hipLaunchKernelGGL((k_explode<L, S, DDF, LAM, 2>), nb, dim3(BLOCK), 0, s, a);
+    else hipLaunchKernelGGL((k_explode<L, S, DDF, LAM>), nb, dim3(BLOCK), 0, s, a);
   }
   static void bcfill(const BArgs &a, hipStream_t s) {
     if (a.count <= 0) return;

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "grid_builder.h"
+#include "grid_device.h"
 #include "lattice.h"
 #include "layout.h"
 #include "lbm.h"
@@ -40,6 +41,9 @@ struct lbm_ctx {
   bool ddf = false, lamf = false;
   // grid
   bool have_grid = false;
+  bool device_build = true;  // build grids and layouts on the GPU (not for host-only contexts)
+  int32_t *d_gslot = nullptr;  // in place on a refined grid: slot -> coalesced slot of its coarse ghost
+  DeviceGridArrays dg;         // canonical tables kept on the device by the device grid build
   HostGrid g;
   DeviceLayout lay;
   lbm_face_bc face[6]{};
@@ -69,8 +73,6 @@ struct lbm_ctx {
   size_t scratch_bytes = 0;
   int parity[8]{};
   bool pre[8]{};
-  int aa_state = 0;  // in-place streaming: 0 own rows hold f_in, 1 rows swapped (after an even step)
-  int gaa = 0;
   bool have_state = false;
   int64_t updates[8]{};
   int64_t coarse_steps = 0;
@@ -142,6 +144,8 @@ void free_device(lbm_ctx *c) {
   c->d_xmask = nullptr;
   c->d_cell_of = c->d_slot_of = c->d_crow = nullptr;
   c->d_flags = nullptr;
+  c->d_gslot = nullptr;
+  c->dg = DeviceGridArrays();
   c->d_sigma = c->d_rhoinf = nullptr;
   c->d_lam = nullptr;
   c->d_ghost = c->d_child = nullptr;
@@ -197,6 +201,8 @@ lbm_status upload(lbm_ctx *c, T **dst, const T *src, size_t count) {
 PhysArgs phys(const lbm_ctx *c, int l) {
   PhysArgs ph{};
   ph.tau = c->tau[l];
+  ph.omega = 1.0 / c->tau[l];
+  ph.krr = 1.0 - 1.0 / c->tau[l];
   ph.cs2w = c->ddf ? c->p.T0 : c->lat.cs2;
   for (int k = 0; k < 6; ++k)
     for (int d = 0; d < 3; ++d)
@@ -227,6 +233,8 @@ Topo topo(const lbm_ctx *c) {
   return t;
 }
 
+bool read_pre(const lbm_ctx *c, int l);
+
 void launch_coalesce(lbm_ctx *c, int l) {
   const int64_t cnt = c->g.goff[l + 1] - c->g.goff[l];
   if (cnt <= 0) return;
@@ -250,7 +258,9 @@ void launch_coalesce(lbm_ctx *c, int l) {
   PhysArgs ph = phys(c, l);
   a.cs2w = ph.cs2w;
   memcpy(a.uw, ph.uw, sizeof a.uw);
-  c->ops.coalesce(a, c->pre[l + 1], c->stream);
+  a.aa = c->p.in_place && c->parity[l + 1] == 1 ? 2 : 0;
+  a.swap = c->p.in_place && c->parity[l] == 1 ? 1 : 0;
+  c->ops.coalesce(a, read_pre(c, l + 1), c->stream);
 }
 
 void launch_explode(lbm_ctx *c, int l) {
@@ -267,6 +277,17 @@ void launch_explode(lbm_ctx *c, int l) {
   a.ghost_cell = c->d_ghost;
   a.g0 = c->g.goff[l];
   a.count = cnt;
+  if (c->p.in_place) {
+    // the fine level has just stepped: odd phase, rows swapped
+    a.mode = c->parity[l + 1] == 1 ? 1 : 2;
+    a.vbase = c->NS;
+    a.xnbr = c->d_xnbr;
+    a.xstride = c->lay.xstride;
+    a.crow = c->d_crow;
+    const PhysArgs ph = phys(c, l + 1);
+    a.cs2w = ph.cs2w;
+    memcpy(a.uw, ph.uw, sizeof a.uw);
+  }
   c->ops.explode(a, c->stream);
 }
 
@@ -329,6 +350,7 @@ KArgs collide_args(lbm_ctx *c, int l, int par) {
   a.count = c->lay.soff[l + 1] - c->lay.soff[l];
   a.ph = phys(c, l);
   a.counters = c->d_counters;
+  a.gslot = c->d_gslot;
   return a;
 }
 
@@ -343,10 +365,10 @@ void launch_collide(lbm_ctx *c, int l) {
       slot.level = l;
       hipEventRecord(slot.a, c->stream);
     }
-    if (c->p.in_place) {
-      a.aa = c->aa_state == 0 ? 1 : 2;
-      c->aa_state ^= 1;
-    }
+    // in place, a level's phase is the parity of its step count: even, its
+    // own rows hold the streamed populations; odd, the post-collision ones
+    // sit swapped in the rows of their opposites
+    if (c->p.in_place) a.aa = c->parity[l] == 0 ? 1 : 2;
     c->ops.collide(a, c->pre[l], c->stream);
     if (c->prof) {
       hipEventRecord(slot.b, c->stream);
@@ -407,11 +429,11 @@ void coalesce_all(lbm_ctx *c) {
 
 // readers of the synchronisation-point state: own rows (pre-collision at
 // start, or the in-place buffer after an odd step), or swapped pulls
-bool read_pre(const lbm_ctx *c, int l) { return c->pre[l] || (c->p.in_place && c->aa_state == 0); }
+bool read_pre(const lbm_ctx *c, int l) { return c->pre[l] || (c->p.in_place && c->parity[l] == 0); }
 
 MArgs gather_args(lbm_ctx *c, int l, int mode) {
   MArgs a{};
-  a.aa = c->p.in_place && c->aa_state == 1 ? 2 : 0;
+  a.aa = c->p.in_place && c->parity[l] == 1 ? 2 : 0;
   a.fin = fbuf(c, l);
   a.gin = gbuf(c, l);
   a.lam = c->d_lam;
@@ -470,6 +492,10 @@ lbm_status mlp_upload_weights(lbm_ctx *c, const float *w) {
   c->have_mlp = true;
   return LBM_OK;
 }
+
+// temporaries of the device grid build, through the context's allocator
+void *build_alloc(size_t bytes, void *ctx) { return dev_alloc((lbm_ctx *)ctx, bytes); }
+void build_release(void *p, void *ctx) { dev_release((lbm_ctx *)ctx, p); }
 
 }  // namespace
 
@@ -530,6 +556,12 @@ void lbm_destroy(lbm_ctx *c) {
 
 const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
+lbm_status lbm_set_device_build(lbm_ctx *c, int on) {
+  if (!c) return LBM_E_ARG;
+  c->device_build = on != 0;
+  return LBM_OK;
+}
+
 lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_levels,
                           const lbm_mask *refine, const lbm_mask *solid,
                           const lbm_face_bc faces[6]) {
@@ -565,8 +597,20 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
     fs[k].sponge_width = faces[k].sponge_width;
   }
   std::string err;
-  const int rc = build_grid(c->lat, dim, ext, n_levels, rv.data(), solid ? sv.data() : nullptr, fs, &c->g, &err);
-  if (rc != 0) return set_err(c, rc == -2 ? LBM_E_MASK : LBM_E_ARG, err);
+  bool periodic[3];
+  for (int a = 0; a < 3; ++a)
+    periodic[a] = a < dim && faces[2 * a].kind == LBM_BC_PERIODIC && faces[2 * a + 1].kind == LBM_BC_PERIODIC;
+  const bool on_device = c->device_build && !c->p.host_only;
+  if (on_device) {
+    // the tree and its layout built on the GPU, copied into c->g / c->lay
+    DevAlloc da{&build_alloc, &build_release, c};
+    const int rc = build_grid_device(c->lat, dim, ext, n_levels, rv.data(), solid ? sv.data() : nullptr, fs,
+                                     periodic, da, c->stream, &c->g, &c->lay, &c->dg, &err);
+    if (rc != 0) return set_err(c, rc == -2 ? LBM_E_MASK : (rc == -3 ? LBM_E_DEVICE : LBM_E_ARG), err);
+  } else {
+    const int rc = build_grid(c->lat, dim, ext, n_levels, rv.data(), solid ? sv.data() : nullptr, fs, &c->g, &err);
+    if (rc != 0) return set_err(c, rc == -2 ? LBM_E_MASK : LBM_E_ARG, err);
+  }
   c->dim = dim;
   c->L = n_levels;
   // relaxation time per level, nu_l = nu_finest / 2^(L-1-l) (acoustic scaling)
@@ -575,12 +619,7 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
     c->tau[l] = c->p.nu_finest <= 0.0 ? 0.5 : c->p.nu_finest / std::ldexp(1.0, n_levels - 1 - l) / cs2e + 0.5;
   c->N = c->g.n;
   c->Ng = c->g.goff[n_levels];
-  {
-    bool periodic[3];
-    for (int a = 0; a < 3; ++a)
-      periodic[a] = a < dim && faces[2 * a].kind == LBM_BC_PERIODIC && faces[2 * a + 1].kind == LBM_BC_PERIODIC;
-    if (build_layout(c->g, c->lat, periodic, &c->lay, &err) != 0) return set_err(c, LBM_E_ARG, err);
-  }
+  if (!on_device && build_layout(c->g, c->lat, periodic, &c->lay, &err) != 0) return set_err(c, LBM_E_ARG, err);
   c->NS = c->lay.nslot;
   c->stride = ((c->NS + c->Ng + 63) / 64) * 64;
   {
@@ -603,13 +642,13 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
   }
   if (c->p.in_place) {
     // one buffer streamed in place: single level, faces without post-collision fills
-    bool ok = n_levels == 1 && c->lat.kind >= 0 && c->p.collision <= LBM_DDF_NEWTON;
+    bool ok = c->lat.kind >= 0 && c->p.collision <= LBM_DDF_NEWTON;
     for (int k = 0; k < 6; ++k)
       ok = ok && (faces[k].kind == LBM_BC_PERIODIC || faces[k].kind == LBM_BC_WALL ||
                   faces[k].kind == LBM_BC_MOVING_WALL) && faces[k].sponge_sigma_max <= 0.0;
     if (!ok)
       return set_err(c, LBM_E_UNSUPPORTED,
-                     "in-place streaming needs one level, periodic / wall faces, no sponge, no surrogate");
+                     "in-place streaming needs periodic / wall faces, no sponge, no surrogate");
   }
   c->have_grid = true;
   if (c->p.host_only) return LBM_OK;
@@ -639,8 +678,14 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
   if ((s = upload(c, &c->d_xbase, y.xbase.data(), y.xbase.size())) != LBM_OK) return s;
   if ((s = upload(c, &c->d_xnbr, y.xnbr.data(), y.xnbr.size())) != LBM_OK) return s;
   if ((s = upload(c, &c->d_cell_of, y.cell_of.data(), y.cell_of.size())) != LBM_OK) return s;
-  if ((s = upload(c, &c->d_slot_of, y.slot_of.data(), y.slot_of.size())) != LBM_OK) return s;
-  {
+  if (c->dg.slot_of) c->d_slot_of = c->dg.slot_of;
+  else if ((s = upload(c, &c->d_slot_of, y.slot_of.data(), y.slot_of.size())) != LBM_OK) return s;
+  if (c->dg.nbr) {
+    c->d_flags = (uint8_t *)dev_alloc(c, std::max<int64_t>(NS, 1));
+    if (!c->d_flags) return set_err(c, LBM_E_NOMEM, "flag allocation failed");
+    launch_slot_flags(c->dg, NS, c->d_flags, c->stream);
+    if ((s = check_launch(c)) != LBM_OK) return s;
+  } else {
     // device flags per slot: the canonical ones, F_MOVING where a population
     // is pulled from a moving wall, F_HOLE for slots without a cell
     std::vector<uint8_t> fl(NS, (uint8_t)F_HOLE);
@@ -690,6 +735,13 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
   }
   if ((s = upload(c, &c->d_unknown, c->g.unknown.data(), c->Ng)) != LBM_OK) return s;
   if ((s = upload(c, &c->d_bc_face, c->g.bc_face.data(), c->g.bc_face.size())) != LBM_OK) return s;
+  if (c->p.in_place && c->Ng > 0) {
+    // where each coarse ghost leaves its post-collision populations for the
+    // explosion when streaming in place: its coalesced slot
+    std::vector<int32_t> gs((size_t)NS, -1);
+    for (int64_t k = 0; k < c->Ng; ++k) gs[y.slot_of[c->g.ghost_cell[k]]] = (int32_t)(NS + k);
+    if ((s = upload(c, &c->d_gslot, gs.data(), gs.size())) != LBM_OK) return s;
+  }
   (void)NCH;
   c->d_counters = (unsigned long long *)dev_alloc(c, sizeof(unsigned long long) * CNT_COUNT * CNT_COPIES);
   if (!c->d_counters) return set_err(c, LBM_E_NOMEM, "counter allocation failed");
@@ -710,6 +762,23 @@ lbm_status lbm_grid_info(lbm_ctx *c, int64_t *n_cells, int64_t *n_per_level, int
     e += (double)k / std::ldexp(1.0, c->L - 1 - l);
   }
   if (eq_fine) *eq_fine = e;
+  return LBM_OK;
+}
+
+lbm_status lbm_layout_export(lbm_ctx *c, int32_t *slot_of, int32_t *xrow_of, int32_t *nbrick, uint64_t *xmask,
+                             int32_t *xnbr) {
+  if (!c) return LBM_E_ARG;
+  if (!c->have_grid) return set_err(c, LBM_E_STATE, "no grid");
+  const DeviceLayout &y = c->lay;
+  const int64_t n = c->g.n, nb = y.nslot / 64, Qm = c->lat.Q - 1;
+  if (slot_of) std::copy(y.slot_of.begin(), y.slot_of.end(), slot_of);
+  if (xrow_of) std::copy(y.xrow_of.begin(), y.xrow_of.end(), xrow_of);
+  if (nbrick) std::copy(y.nbrick.begin(), y.nbrick.begin() + nb * y.nbp, nbrick);
+  if (xmask) std::copy(y.xmask.begin(), y.xmask.begin() + nb, xmask);
+  if (xnbr)
+    for (int64_t i = 0; i < Qm; ++i)
+      std::copy(y.xnbr.begin() + i * y.xstride, y.xnbr.begin() + i * y.xstride + y.nx, xnbr + i * y.nx);
+  (void)n;
   return LBM_OK;
 }
 
@@ -736,6 +805,11 @@ lbm_status lbm_grid_export(lbm_ctx *c, int32_t *coords, int8_t *level, uint8_t *
   if (!c->have_grid) return set_err(c, LBM_E_STATE, "no grid");
   const int64_t n = c->N;
   const int Qm = c->lat.Q - 1;
+  if (coords || nbr) {
+    // a device-built grid keeps its coordinates and neighbour list there
+    std::string err;
+    if (fetch_host_mirror(c->dg, &c->g, c->stream, &err) != 0) return set_err(c, LBM_E_DEVICE, err);
+  }
   if (coords) memcpy(coords, c->g.xyz.data(), sizeof(int32_t) * 3 * n);
   if (level) memcpy(level, c->g.lev.data(), n);
   if (flags) memcpy(flags, c->g.flag.data(), n);
@@ -797,7 +871,6 @@ static lbm_status init_common(lbm_ctx *c, const double *src, const double *src_g
   for (int l = 0; l < c->L; ++l) {
     c->parity[l] = 0;
     c->pre[l] = true;
-    c->aa_state = 0;
     c->updates[l] = 0;
   }
   c->coarse_steps = 0;
@@ -839,7 +912,7 @@ lbm_status lbm_sensor(lbm_ctx *c, double *eps) {
 lbm_status lbm_remesh(lbm_ctx *c, const lbm_mask *refine, const lbm_mask *solid) {
   lbm_status s = need_state(c);
   if (s != LBM_OK) return s;
-  if (c->p.in_place) return set_err(c, LBM_E_UNSUPPORTED, "in-place streaming runs on one level only");
+  if (c->p.in_place) return set_err(c, LBM_E_UNSUPPORTED, "remeshing keeps two population buffers (no in-place streaming)");
   if (c->L > 1 && !refine) return set_err(c, LBM_E_ARG, "refine masks missing");
   std::vector<float> mlpw;
   if (c->have_mlp) {
@@ -875,7 +948,28 @@ lbm_status lbm_remesh(lbm_ctx *c, const lbm_mask *refine, const lbm_mask *solid)
     release_old();
     return s;
   }
-  // 2. the new tree: same extent, levels and faces
+  // 2. the new tree: same extent, levels and faces.  The old tree's device
+  // tables (a device-built grid) are taken out of the context's allocations
+  // so that the new build leaves them for the source lists.
+  DeviceGridArrays old_dg = c->dg;
+  for (void *p : {(void *)old_dg.xyz, (void *)old_dg.lev, (void *)old_dg.flag, (void *)old_dg.nbr,
+                  (void *)old_dg.slot_of})
+    for (size_t k = 0; p && k < c->allocs.size(); ++k)
+      if (c->allocs[k] == p) {
+        c->allocs.erase(c->allocs.begin() + k);
+        break;
+      }
+  if (c->d_slot_of == old_dg.slot_of) c->d_slot_of = nullptr;
+  auto release_old_dg = [&]() {
+    for (void *p : {(void *)old_dg.xyz, (void *)old_dg.lev, (void *)old_dg.flag, (void *)old_dg.nbr,
+                    (void *)old_dg.slot_of})
+      if (p) {
+        hipStreamSynchronize(c->stream);
+        if (c->dfree) c->dfree(p, c->actx);
+        else hipFree(p);
+      }
+    old_dg = DeviceGridArrays();
+  };
   HostGrid prev = std::move(c->g);
   lbm_face_bc faces[6];
   for (int k = 0; k < 6; ++k) faces[k] = c->face[k];
@@ -885,34 +979,54 @@ lbm_status lbm_remesh(lbm_ctx *c, const lbm_mask *refine, const lbm_mask *solid)
   s = lbm_grid_build(c, prev.D, prev.ext, prev.L, refine, solid, faces);
   if (s != LBM_OK) {
     release_old();
+    release_old_dg();
     return s;
   }
   // 3. where every new cell takes its state from
-  std::vector<int64_t> off;
-  std::vector<int32_t> src;
-  std::vector<double> wt;
-  std::string err;
-  if (remesh_sources(prev, c->g, &off, &src, &wt, &err) != 0) {
-    release_old();
-    c->have_state = false;
-    return set_err(c, LBM_E_MASK, err);
-  }
-  // 4. move it across on the device and start the new tree from it
   int64_t *d_off = nullptr;
   int32_t *d_src = nullptr;
   double *d_wt = nullptr;
   auto release_all = [&]() {
     release_old();
+    release_old_dg();
     dev_release(c, d_off);
     dev_release(c, d_src);
     dev_release(c, d_wt);
   };
-  if ((s = upload(c, &d_off, off.data(), off.size())) != LBM_OK ||
-      (s = upload(c, &d_src, src.data(), src.size())) != LBM_OK ||
-      (s = upload(c, &d_wt, wt.data(), wt.size())) != LBM_OK) {
-    release_all();
-    return s;
+  std::string err;
+  if (old_dg.xyz && c->dg.xyz) {
+    // on the device, from the two trees' coordinates, levels and flags
+    DevAlloc da{&build_alloc, &build_release, c};
+    const int rc = remesh_sources_device(prev, old_dg, c->g, c->dg, da, c->stream, &d_off, &d_src, &d_wt, &err);
+    if (rc != 0) {
+      release_all();
+      if (rc != -1) return set_err(c, LBM_E_DEVICE, err);
+      c->have_state = false;
+      return set_err(c, LBM_E_MASK, err);
+    }
+  } else {
+    std::vector<int64_t> off;
+    std::vector<int32_t> src;
+    std::vector<double> wt;
+    // host lists need both trees' coordinates on the host
+    if (fetch_host_mirror(old_dg, &prev, c->stream, &err) != 0 ||
+        fetch_host_mirror(c->dg, &c->g, c->stream, &err) != 0) {
+      release_all();
+      return set_err(c, LBM_E_DEVICE, err);
+    }
+    if (remesh_sources(prev, c->g, &off, &src, &wt, &err) != 0) {
+      release_all();
+      c->have_state = false;
+      return set_err(c, LBM_E_MASK, err);
+    }
+    if ((s = upload(c, &d_off, off.data(), off.size())) != LBM_OK ||
+        (s = upload(c, &d_src, src.data(), src.size())) != LBM_OK ||
+        (s = upload(c, &d_wt, wt.data(), wt.size())) != LBM_OK) {
+      release_all();
+      return s;
+    }
   }
+  // 4. move it across on the device and start the new tree from it
   const int64_t n_new = c->N;
   double *nw = scratch(c, sizeof(double) * (size_t)rows * (size_t)std::max<int64_t>(n_new, 1));
   if (!nw) {
@@ -976,6 +1090,8 @@ void launch_collide_fused(lbm_ctx *c, int t) {
     m.begin[k] = c->lay.soff[l];
     m.count[k] = c->lay.soff[l + 1] - c->lay.soff[l];
     m.tau[k] = c->tau[l];
+    m.omega[k] = 1.0 / c->tau[l];
+    m.krr[k] = 1.0 - 1.0 / c->tau[l];
     m.block0[k] = nb;
     nb += ((m.count[k] + cb - 1) / cb + 7) / 8 * 8;  // a multiple of 8 blocks per level
   }
@@ -1030,11 +1146,10 @@ bool graph_ready(lbm_ctx *c) {
   if (c->gexec) {
     bool same = true;
     for (int l = 0; l < c->L; ++l) same = same && c->gparity[l] == c->parity[l];
-    if (same && c->gaa == c->aa_state) return true;
+    if (same) return true;
     drop_graph(c);
   }
   int par[8];
-  const int aa = c->aa_state;
   int64_t upd[8], cs = c->coarse_steps;
   for (int l = 0; l < 8; ++l) {
     par[l] = c->parity[l];
@@ -1050,7 +1165,6 @@ bool graph_ready(lbm_ctx *c) {
     c->updates[l] = upd[l];
   }
   c->coarse_steps = cs;
-  c->aa_state = aa;
   if (e != hipSuccess || !g) {
     hipGetLastError();
     return false;
@@ -1064,7 +1178,6 @@ bool graph_ready(lbm_ctx *c) {
   }
   c->gexec = x;
   for (int l = 0; l < c->L; ++l) c->gparity[l] = c->parity[l];
-  c->gaa = c->aa_state;
   return true;
 }
 

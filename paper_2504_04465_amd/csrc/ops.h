@@ -35,6 +35,7 @@ struct FaceVals {
 
 struct PhysArgs {
   double tau;          // relaxation time of the level
+  double omega, krr;   // 1 / tau and 1 - 1 / tau, formed on the host
   double cs2w;         // denominator of the moving-wall term (cs2, or T0 for DDF)
   double uw[6][3];     // moving-wall velocity per face
   double Cv, sensor_A; // DDF
@@ -63,7 +64,7 @@ struct MultiTable {
   int parity[MAX_LEVELS];   // input buffer of each active level
   const void *f[2], *g[2];  // the two population buffers
   int64_t begin[MAX_LEVELS], count[MAX_LEVELS];
-  double tau[MAX_LEVELS];
+  double tau[MAX_LEVELS], omega[MAX_LEVELS], krr[MAX_LEVELS];
   int64_t block0[MAX_LEVELS + 1];  // first block of each (multiples of 8); block0[n] = grid size
 };
 
@@ -85,6 +86,10 @@ struct KArgs {
   PhysArgs ph;
   unsigned long long *counters;
   int aa;              // in-place streaming: 0 off, 1 even step, 2 odd step
+  // in place on a refined grid: slot -> coalesced slot of a coarse ghost
+  // (-1 elsewhere); a ghost leaves its post-collision populations there,
+  // row i, for the explosion
+  const int32_t *gslot;
   MultiTable multi;    // n > 0: every active level of a substep in one launch
 };
 
@@ -106,6 +111,10 @@ struct CArgs {
   int64_t g0, count;        // ghosts [g0, g0 + count)
   double cs2w, uw[6][3];
   int ngrp;                 // population groups per child (set by the launcher)
+  // in-place streaming: aa = 2 when the fine level's rows are swapped (odd
+  // phase: the children are read as a swapped pull); swap = 1 when the
+  // coarse level's are (the coalesced population i goes to row opp(i))
+  int aa, swap;
 };
 
 // uniform explosion of coarse-ghost post-collision states into the children
@@ -118,6 +127,17 @@ struct EArgs {
   int64_t stride;
   const int32_t *child, *ghost_cell;
   int64_t g0, count;
+  // in-place streaming (mode 0: two buffers): the coarse ghost's
+  // post-collision populations are read from its coalesced slot (vbase +
+  // ghost index, where its collide left them); mode 1, the fine level is at
+  // an odd phase: child row opp(i) takes population i; mode 2, even phase:
+  // population i goes to row i of the cell that pulls it from the child
+  // (through the child's exception row), the bounce-back into the child's
+  // own row opp(i) with the moving-wall term
+  int mode;
+  int64_t vbase, xstride;
+  const int32_t *xnbr, *crow;
+  double cs2w, uw[6][3];
 };
 
 // boundary-layer fill after the collision of one level

@@ -40,21 +40,24 @@ struct SumCounts {
   int nb[SUM_LEVELS];
 };
 
-// one thread per quantity adds the partials level by level, block by block:
-// a fixed order, so every caller gets the same bits
-__global__ void k_sum_partials(const double *partials, SumCounts cnt, int n_levels, double *out) {
-  const int k = threadIdx.x;
-  if (k >= SUM_Q) return;
+// one wavefront per quantity: lane j adds the partials j, j + 64, ... of
+// every level in turn, then the lanes are combined by a butterfly; a fixed
+// order, so every caller gets the same bits
+__global__ void __launch_bounds__(64 * SUM_Q) k_sum_partials(const double *partials, SumCounts cnt, int n_levels,
+                                                             double *out) {
+  const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double v = 0.0;
   for (int l = 0; l < n_levels; ++l)
-    for (int b = 0; b < cnt.nb[l]; ++b) v += partials[((int64_t)l * SUM_BLOCKS + b) * SUM_Q + k];
-  out[k] = v;
+    for (int b = lane; b < cnt.nb[l]; b += 64) v += partials[((int64_t)l * SUM_BLOCKS + b) * SUM_Q + k];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (lane == 0) out[k] = v;
 }
 
 void launch_sum_partials(const double *partials, const int *nb, int n_levels, double *out, hipStream_t s) {
   SumCounts cnt{};
   for (int l = 0; l < n_levels && l < SUM_LEVELS; ++l) cnt.nb[l] = nb[l];
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, partials, cnt, n_levels, out);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64 * SUM_Q), 0, s, partials, cnt, n_levels, out);
 }
 
 }  // namespace lbm

@@ -26,9 +26,10 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_MASK", -3: "LBM_E_NOMEM", -4:
           -5: "LBM_E_STATE", -6: "LBM_E_NUMERIC", -7: "LBM_E_UNSUPPORTED"}
 
 # every entry point declared in include/lbm.h
-EXPORTS = ["lbm_create", "lbm_grid_build", "lbm_grid_info", "lbm_layout_info", "lbm_grid_export", "lbm_init",
+EXPORTS = ["lbm_create", "lbm_grid_build", "lbm_grid_info", "lbm_layout_info", "lbm_layout_export",
+           "lbm_grid_export", "lbm_init",
            "lbm_step", "lbm_set_face_bc", "lbm_set_graphs", "lbm_moments", "lbm_moments_device", "lbm_stats_get",
-           "lbm_sums_device", "lbm_set_level_fusion", "lbm_set_inflow_noise",
+           "lbm_sums_device", "lbm_set_level_fusion", "lbm_set_inflow_noise", "lbm_set_device_build",
            "lbm_sync", "lbm_profile_enable", "lbm_profile_read", "lbm_get_state", "lbm_get_cells", "lbm_set_state",
            "lbm_remesh", "lbm_sensor",
            "lbm_last_error", "lbm_destroy", "lbm_mlp_set_weights", "lbm_mlp_get_weights",
@@ -89,12 +90,14 @@ def lib():
         L.lbm_grid_build.argtypes = [vp, C.c_int, vp, C.c_int, vp, vp, vp]
         L.lbm_grid_info.argtypes = [vp, vp, vp, vp, vp]
         L.lbm_layout_info.argtypes = [vp, vp, vp, vp, vp]
+        L.lbm_layout_export.argtypes = [vp] * 6
         L.lbm_grid_export.argtypes = [vp] + [vp] * 6
         L.lbm_init.argtypes = [vp, vp]
         L.lbm_step.argtypes = [vp, i64]
         L.lbm_set_face_bc.argtypes = [vp, C.c_int, C.POINTER(FaceBC)]
         L.lbm_set_graphs.argtypes = [vp, C.c_int]
         L.lbm_set_level_fusion.argtypes = [vp, C.c_int]
+        L.lbm_set_device_build.argtypes = [vp, C.c_int]
         L.lbm_set_inflow_noise.argtypes = [vp, vp]
         L.lbm_moments.argtypes = [vp, vp]
         L.lbm_moments_device.argtypes = [vp, vp]
@@ -305,6 +308,19 @@ class LBM:
         return dict(slots=ns.value, exception_rows=nx.value, slots_per_level=spl[: self.n_levels].tolist(),
                     rows_per_level=rpl[: self.n_levels].tolist())
 
+    def layout_export(self):
+        """the brick layout's tables (slot of each cell, exception rows,
+        neighbour bricks, exception masks, pull sources of the rows)"""
+        info = self.layout()
+        nb, nx = info["slots"] // 64, info["exception_rows"]
+        nbp = 32 if self.dim == 3 else 16
+        d = dict(slot_of=np.zeros(self.n, np.int32), xrow_of=np.zeros(self.n, np.int32),
+                 nbrick=np.zeros((nb, nbp), np.int32), xmask=np.zeros(nb, np.uint64),
+                 xnbr=np.zeros((self.Q - 1, nx), np.int32))
+        self._check(self._L.lbm_layout_export(self.h, _ptr(d["slot_of"]), _ptr(d["xrow_of"]), _ptr(d["nbrick"]),
+                                              _ptr(d["xmask"]), _ptr(d["xnbr"])), "lbm_layout_export")
+        return d
+
     def export(self, parts=("coords", "level", "flags", "nbr", "child", "bc_src")):
         """canonical grid tables; `parts` selects which (the neighbour list of
         a large grid is big)"""
@@ -355,6 +371,10 @@ class LBM:
         d = np.ascontiguousarray(du, dtype=np.float64)
         assert d.shape == (3, self.n)
         self._check(self._L.lbm_set_inflow_noise(self.h, _ptr(d)), "lbm_set_inflow_noise")
+
+    def device_build(self, on=True):
+        """build the tree and its layout on the GPU (default) or on the host"""
+        self._check(self._L.lbm_set_device_build(self.h, int(on)), "lbm_set_device_build")
 
     def level_fusion(self, on=True):
         """one collide launch for all levels active at a substep"""

@@ -24,6 +24,12 @@ def cavity(lattice, collision):
     return W.cavity(n=48, levels=1, lattice=lattice, collision=collision)
 
 
+def refined(lattice, collision, n, levels, T0=1.0):
+    w = W.shear(n=n, levels=levels, lattice=lattice, collision=collision, kind="random", u0=0.03, nu_finest=0.02,
+                T0=T0)
+    return w
+
+
 CASES = [("shear D2Q9 RR", lambda: one_level("D2Q9", "RR", 32), "fp32"),
          ("shear D2Q9 BGK", lambda: one_level("D2Q9", "BGK", 32), "fp64"),
          ("shear D3Q27 RR", lambda: one_level("D3Q27", "RR", 12), "fp32"),
@@ -32,7 +38,18 @@ CASES = [("shear D2Q9 RR", lambda: one_level("D2Q9", "RR", 32), "fp32"),
          ("shear D2Q37 DDF", lambda: one_level("D2Q37", "DDF_POLY", 32), "fp32"),
          ("shear D2Q21 Newton", lambda: one_level("D2Q21", "DDF_NEWTON", 32, T0=0.65), "fp64"),
          ("cavity D2Q9 BGK", lambda: cavity("D2Q9", "BGK"), "fp64"),
-         ("cavity D2Q21 RR", lambda: cavity("D2Q21", "RR"), "fp32")]
+         ("cavity D2Q21 RR", lambda: cavity("D2Q21", "RR"), "fp32"),
+         # across refinement interfaces: coalescence, explosion and the
+         # fine ghosts' own links read and written in each level's phase
+         ("refined shear D2Q9 RR 3 levels", lambda: refined("D2Q9", "RR", 32, 3), "fp32"),
+         ("refined shear D2Q9 BGK 3 levels", lambda: refined("D2Q9", "BGK", 32, 3), "fp64"),
+         ("refined shear D3Q27 RR", lambda: refined("D3Q27", "RR", 12, 2), "fp32"),
+         ("refined shear D3Q27 RR fp16", lambda: refined("D3Q27", "RR", 12, 2), "fp16"),
+         ("refined shear D2Q13 RR", lambda: refined("D2Q13", "RR", 32, 3), "fp64"),
+         ("refined shear D2Q37 DDF", lambda: refined("D2Q37", "DDF_POLY", 32, 2), "fp32"),
+         ("refined shear D2Q21 Newton", lambda: refined("D2Q21", "DDF_NEWTON", 32, 2, T0=0.65), "fp64"),
+         ("refined cavity D2Q9 BGK (the 64 x 64 cavity, walls and lid)", lambda: W.cavity(n=64, steps=1), "fp64"),
+         ("refined cavity D2Q9 RR fp32", lambda: W.cavity(n=64, steps=1, collision="RR", storage="fp32"), "fp32")]
 
 
 def pair(w, storage):
@@ -80,6 +97,28 @@ def test_in_place_graph_replay_and_oracle():
         assert np.array_equal(a.moments(), b.moments(), equal_nan=True)
     err = compare(b.moments(), o.moments(), e["level"], 2)
     say(f"[in-place] cavity D2Q9 RR fp64 vs oracle after 14 steps: {err}")
+    assert err["u"] <= 1e-12 and err["rho"] <= 1e-12, err
+    a.close()
+    b.close()
+
+
+def test_in_place_refined_graph_replay_and_oracle():
+    """the two-level 64 x 64 cavity (walls, moving lid, an interface meeting
+    both side walls) streamed in place and replayed from HIP graphs: equal
+    to two buffers bit for bit, and to the oracle at the FP64 bar"""
+    w = W.cavity(n=64, steps=1)
+    a, b = pair(w, "fp64")
+    o = Oracle.from_workload(w)
+    e = o.export()
+    o.init(w.initial_moments(e["coords"], e["level"]))
+    b.graphs(True)
+    for n in (3, 4, 7):
+        a.step(n)
+        b.step(n)
+        o.step(n)
+        assert np.array_equal(a.moments(), b.moments(), equal_nan=True)
+    err = compare(b.moments(), o.moments(), e["level"], 2)
+    say(f"[in-place] refined cavity D2Q9 BGK fp64 vs oracle after 14 steps: {err}")
     assert err["u"] <= 1e-12 and err["rho"] <= 1e-12, err
     a.close()
     b.close()

@@ -149,10 +149,14 @@ def test_brick_layout_uniform_periodic_needs_no_rows():
 
 
 def test_in_place_streaming_limits():
-    """in-place streaming is refused for refined grids and open faces"""
+    """in-place streaming is refused for open faces (boundary layers and
+    sponges would need their fills in both phases) and accepted on refined
+    grids with periodic, wall and moving-wall faces"""
     w = W.shear(n=16, levels=2, lattice="D2Q9", collision="RR")
+    s = B.LBM.from_workload(w, host_only=True, in_place=True)
+    assert s.n_levels == 2
     with pytest.raises(B.LbmError) as e:
-        B.LBM.from_workload(w, host_only=True, in_place=True)
+        B.LBM.from_workload(W.cylinder(scale=16, steps=1), host_only=True, in_place=True)
     assert e.value.code == -7
     w = W.cavity(n=16, levels=1)
     w.faces[0] = W.Face("neumann")
@@ -161,3 +165,29 @@ def test_in_place_streaming_limits():
     assert e.value.code == -7
     s = B.LBM.from_workload(W.cavity(n=16, levels=1), host_only=True, in_place=True)
     assert s.n == 256
+
+
+@pytest.mark.parametrize("name,w", [c for c in cases() if c[0] in ("cyl", "sphere", "ragged3d", "sod")],
+                         ids=["cyl", "sphere", "ragged3d", "sod"])
+def test_layout_export_is_consistent(name, w):
+    """lbm_layout_export on a host-built grid: every cell owns one slot of
+    its level's range, the exception rows are numbered brick by brick in
+    lane order, and the masks count them"""
+    s = B.LBM.from_workload(w, host_only=True)
+    info = s.layout()
+    d = s.layout_export()
+    slot = d["slot_of"].astype(np.int64)
+    assert len(np.unique(slot)) == s.n and slot.min() >= 0 and slot.max() < info["slots"]
+    lev = s.export(("level",))["level"]
+    bounds = np.concatenate([[0], np.cumsum(info["slots_per_level"])])
+    assert np.all(slot >= bounds[lev]) and np.all(slot < bounds[lev + 1])
+    rows = d["xrow_of"]
+    has = rows >= 0
+    assert has.sum() == info["exception_rows"]
+    assert np.array_equal(np.sort(rows[has]), np.arange(info["exception_rows"]))
+    bits = np.array([bin(int(v)).count("1") for v in d["xmask"]])
+    assert bits.sum() == info["exception_rows"]
+    # rows follow the slots of their cells
+    order = np.argsort(slot[has])
+    assert np.all(np.diff(rows[has][order]) > 0)
+    s.close()
