@@ -1441,7 +1441,42 @@ __device__ inline T6 pick6(const T6 (&v)[6], int k) {
   return r;
 }
 
-template <class L, int COLL, class S>
+// store of a cell's post-collision value v of population i in place at an
+// even phase (MODE 2 of the fills): to row i of the cell that pulls it
+// (through the cell's exception row), back into the cell's row opp(i) with
+// the moving-wall term at a wall, into its own row i when it pulls that
+// population from itself.  RAW copies storage values unchanged where no
+// arithmetic applies.  G: the second distribution (stored without the
+// weight shift, bounced back without the moving-wall term).
+template <class L, class S, bool G = false>
+__device__ inline void push_value(S *f, int64_t stride, int64_t c, const int32_t *xnbr, int64_t xstride, int64_t row,
+                                  int i, typename Sto<S>::C v, S raw, bool use_raw, const double (&uw)[6][3],
+                                  double cs2w) {
+  using C = typename Sto<S>::C;
+  const int j = L::S.opp[i];
+  const double wi = G ? 0.0 : L::S.w[i];
+  if (xnbr[(int64_t)(i - 1) * xstride + row] == (int32_t)c) {
+    if (use_raw) f[(int64_t)i * stride + c] = raw;
+    else Sto<S>::st(f, (int64_t)i * stride + c, v, wi);
+  }
+  const int32_t s = xnbr[(int64_t)(j - 1) * xstride + row];
+  if (s == (int32_t)c) return;
+  if (s >= 0) {
+    if (use_raw) f[(int64_t)i * stride + s] = raw;
+    else Sto<S>::st(f, (int64_t)i * stride + s, v, wi);
+  } else if (G) {
+    if (use_raw) f[(int64_t)j * stride + c] = raw;
+    else Sto<S>::st(f, (int64_t)j * stride + c, v, 0.0);
+  } else {
+    C w = use_raw ? Sto<S>::ldv(raw, L::S.w[i]) : v;
+    if (s <= -2) w += (C)(2.0 * L::S.w[j] * wall_dot<L>(uw, -2 - s, j) / cs2w);
+    Sto<S>::st(f, (int64_t)j * stride + c, w, L::S.w[j]);
+  }
+}
+
+// MODE 0: two buffers; 1, 2: in place, the level at an odd / even phase
+// after its step (see BArgs)
+template <class L, int COLL, class S, int MODE = 0>
 __global__ void __launch_bounds__(BLOCK) k_bcfill(const BArgs a) {
   using C = typename Sto<S>::C;
   constexpr bool DDF = COLL >= COLL_DDF_POLY;
@@ -1453,6 +1488,10 @@ __global__ void __launch_bounds__(BLOCK) k_bcfill(const BArgs a) {
   const int face = a.bc_face[k];
   S *f = (S *)a.f;
   S *g = (S *)a.g;
+  // where population i of the source and of the cell live
+  const int64_t sbase = MODE == 2 ? (int64_t)a.stage[src] : src;
+  auto srow = [&](int i) -> int64_t { return MODE == 1 ? L::S.opp[i] : i; };
+  const int64_t row = MODE == 2 ? (int64_t)a.bc_row[k] : 0;
   int kind = 0;
 #pragma unroll
   for (int q = 0; q < 6; ++q)
@@ -1465,15 +1504,25 @@ __global__ void __launch_bounds__(BLOCK) k_bcfill(const BArgs a) {
   if (kind < 0) {  // Neumann: all loads, then all stores
     S v[L::Q], vg[DDF ? L::Q : 1];
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) v[i] = f[(int64_t)i * a.stride + src];
+    for (int i = 0; i < L::Q; ++i) v[i] = f[srow(i) * a.stride + sbase];
     if (DDF)
 #pragma unroll
-      for (int i = 0; i < L::Q; ++i) vg[i] = g[(int64_t)i * a.stride + src];
+      for (int i = 0; i < L::Q; ++i) vg[i] = g[srow(i) * a.stride + sbase];
+    if constexpr (MODE == 2) {
+      f[c] = v[0];
+      if (DDF) g[c] = vg[0];
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) f[(int64_t)i * a.stride + c] = v[i];
-    if (DDF)
+      for (int i = 1; i < L::Q; ++i) {
+        push_value<L, S>(f, a.stride, c, a.xnbr, a.xstride, row, i, (C)0, v[i], true, a.ph.uw, a.ph.cs2w);
+        if (DDF) push_value<L, S, true>(g, a.stride, c, a.xnbr, a.xstride, row, i, (C)0, vg[i], true, a.ph.uw, 1.0);
+      }
+    } else {
 #pragma unroll
-      for (int i = 0; i < L::Q; ++i) g[(int64_t)i * a.stride + c] = vg[i];
+      for (int i = 0; i < L::Q; ++i) f[srow(i) * a.stride + c] = v[i];
+      if (DDF)
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) g[srow(i) * a.stride + c] = vg[i];
+    }
     if (LAM)
 #pragma unroll
       for (int q = 0; q < NLAM; ++q) ((LamT<S> *)a.lam)[(int64_t)q * a.stride + c] = ((LamT<S> *)a.lam)[(int64_t)q * a.stride + src];
@@ -1483,7 +1532,7 @@ __global__ void __launch_bounds__(BLOCK) k_bcfill(const BArgs a) {
   if (kind == 1) {
     rho = (C)0;
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) rho += Sto<S>::ld(f, (int64_t)i * a.stride + src, L::S.w[i]);
+    for (int i = 0; i < L::Q; ++i) rho += Sto<S>::ld(f, srow(i) * a.stride + sbase, L::S.w[i]);
   }
   C u[3] = {(C)fu[0], (C)fu[1], (C)fu[2]};
   C feq[L::Q], geq[DDF ? L::Q : 1];
@@ -1497,10 +1546,20 @@ __global__ void __launch_bounds__(BLOCK) k_bcfill(const BArgs a) {
 #pragma unroll
     for (int q = 0; q < NLAM; ++q) ((LamT<S> *)a.lam)[(int64_t)q * a.stride + c] = (LamT<S>)lam[q];
   }
+  if constexpr (MODE == 2) {
+    Sto<S>::st(f, c, feq[0], L::S.w[0]);
+    if (DDF) Sto<S>::st(g, c, geq[0], 0.0);
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) {
-    Sto<S>::st(f, (int64_t)i * a.stride + c, feq[i], L::S.w[i]);
-    if (DDF) Sto<S>::st(g, (int64_t)i * a.stride + c, geq[i], 0.0);
+    for (int i = 1; i < L::Q; ++i) {
+      push_value<L, S>(f, a.stride, c, a.xnbr, a.xstride, row, i, feq[i], S(), false, a.ph.uw, a.ph.cs2w);
+      if (DDF) push_value<L, S, true>(g, a.stride, c, a.xnbr, a.xstride, row, i, geq[i], S(), false, a.ph.uw, 1.0);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+      Sto<S>::st(f, srow(i) * a.stride + c, feq[i], L::S.w[i]);
+      if (DDF) Sto<S>::st(g, srow(i) * a.stride + c, geq[i], 0.0);
+    }
   }
 }
 
@@ -1788,7 +1847,10 @@ struct Launch {
   }
   static void bcfill(const BArgs &a, hipStream_t s) {
     if (a.count <= 0) return;
-    hipLaunchKernelGGL((k_bcfill<L, COLL, S>), dim3(nblocks(a.count)), dim3(BLOCK), 0, s, a);
+    const dim3 nb(nblocks(a.count));
+    if (a.mode == 1) hipLaunchKernelGGL((k_bcfill<L, COLL, S, 1>), nb, dim3(BLOCK), 0, s, a);
+    else if (a.mode == 2) hipLaunchKernelGGL((k_bcfill<L, COLL, S, 2>), nb, dim3(BLOCK), 0, s, a);
+    else hipLaunchKernelGGL((k_bcfill<L, COLL, S>), nb, dim3(BLOCK), 0, s, a);
   }
   static void gather(const MArgs &a, bool pre, hipStream_t s) {
     if (a.count <= 0) return;

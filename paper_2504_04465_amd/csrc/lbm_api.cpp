@@ -42,8 +42,10 @@ struct lbm_ctx {
   // grid
   bool have_grid = false;
   bool device_build = true;  // build grids and layouts on the GPU (not for host-only contexts)
-  int32_t *d_gslot = nullptr;  // in place on a refined grid: slot -> coalesced slot of its coarse ghost
+  int32_t *d_gslot = nullptr;  // in place: slot -> staging slot (see stage)
+  int32_t *d_bc_row = nullptr; // in place: exception row of each boundary-layer cell
   DeviceGridArrays dg;         // canonical tables kept on the device by the device grid build
+  std::vector<int32_t> stage;  // in place: slot -> staging slot (coarse ghosts, boundary sources), or -1
   HostGrid g;
   DeviceLayout lay;
   lbm_face_bc face[6]{};
@@ -145,6 +147,7 @@ void free_device(lbm_ctx *c) {
   c->d_cell_of = c->d_slot_of = c->d_crow = nullptr;
   c->d_flags = nullptr;
   c->d_gslot = nullptr;
+  c->d_bc_row = nullptr;
   c->dg = DeviceGridArrays();
   c->d_sigma = c->d_rhoinf = nullptr;
   c->d_lam = nullptr;
@@ -318,6 +321,14 @@ void launch_bcfill(lbm_ctx *c, int l) {
   a.fv = face_vals(c);
   a.ph = phys(c, l);
   a.counters = c->d_counters;
+  if (c->p.in_place) {
+    // the level has just stepped: odd phase, rows swapped
+    a.mode = c->parity[l] == 1 ? 1 : 2;
+    a.stage = c->d_gslot;
+    a.bc_row = c->d_bc_row;
+    a.xnbr = c->d_xnbr;
+    a.xstride = c->lay.xstride;
+  }
   c->ops.bcfill(a, c->stream);
 }
 
@@ -621,7 +632,21 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
   c->Ng = c->g.goff[n_levels];
   if (!on_device && build_layout(c->g, c->lat, periodic, &c->lay, &err) != 0) return set_err(c, LBM_E_ARG, err);
   c->NS = c->lay.nslot;
-  c->stride = ((c->NS + c->Ng + 63) / 64) * 64;
+  // in place, every coarse ghost and every boundary-layer source cell gets
+  // a staging slot for its post-collision populations (explosion, boundary
+  // fill): the ghosts their coalesced slot, the sources slots of their own
+  // after those
+  c->stage.clear();
+  int64_t nstage = 0;
+  if (c->p.in_place && (c->Ng > 0 || !c->g.bc_src.empty())) {
+    c->stage.assign((size_t)c->NS, -1);
+    for (int64_t k = 0; k < c->Ng; ++k) c->stage[c->lay.slot_of[c->g.ghost_cell[k]]] = (int32_t)(c->NS + k);
+    for (size_t k = 0; k < c->g.bc_src.size(); ++k) {
+      const int32_t ss = c->lay.slot_of[c->g.bc_src[k]];
+      if (c->stage[ss] < 0) c->stage[ss] = (int32_t)(c->NS + c->Ng + nstage++);
+    }
+  }
+  c->stride = ((c->NS + c->Ng + nstage + 63) / 64) * 64;
   {
     // bytes one update of level l must move at least: its populations in
     // and out (and multipliers), plus the level's share of the flag, brick
@@ -640,16 +665,8 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
       c->bpu[l] = ncell > 0 ? pops + tables / (double)ncell : pops;
     }
   }
-  if (c->p.in_place) {
-    // one buffer streamed in place: single level, faces without post-collision fills
-    bool ok = c->lat.kind >= 0 && c->p.collision <= LBM_DDF_NEWTON;
-    for (int k = 0; k < 6; ++k)
-      ok = ok && (faces[k].kind == LBM_BC_PERIODIC || faces[k].kind == LBM_BC_WALL ||
-                  faces[k].kind == LBM_BC_MOVING_WALL) && faces[k].sponge_sigma_max <= 0.0;
-    if (!ok)
-      return set_err(c, LBM_E_UNSUPPORTED,
-                     "in-place streaming needs periodic / wall faces, no sponge, no surrogate");
-  }
+  if (c->p.in_place && !(c->lat.kind >= 0 && c->p.collision <= LBM_DDF_NEWTON))
+    return set_err(c, LBM_E_UNSUPPORTED, "in-place streaming: not with the surrogate");
   c->have_grid = true;
   if (c->p.host_only) return LBM_OK;
   // ---- device upload ----------------------------------------------------
@@ -735,12 +752,17 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
   }
   if ((s = upload(c, &c->d_unknown, c->g.unknown.data(), c->Ng)) != LBM_OK) return s;
   if ((s = upload(c, &c->d_bc_face, c->g.bc_face.data(), c->g.bc_face.size())) != LBM_OK) return s;
-  if (c->p.in_place && c->Ng > 0) {
-    // where each coarse ghost leaves its post-collision populations for the
-    // explosion when streaming in place: its coalesced slot
-    std::vector<int32_t> gs((size_t)NS, -1);
-    for (int64_t k = 0; k < c->Ng; ++k) gs[y.slot_of[c->g.ghost_cell[k]]] = (int32_t)(NS + k);
-    if ((s = upload(c, &c->d_gslot, gs.data(), gs.size())) != LBM_OK) return s;
+  if (!c->stage.empty()) {
+    // where coarse ghosts and boundary-layer sources leave their
+    // post-collision populations when streaming in place
+    if ((s = upload(c, &c->d_gslot, c->stage.data(), c->stage.size())) != LBM_OK) return s;
+    // exception row of each boundary-layer cell (its pushes go through it)
+    std::vector<int32_t> br(c->g.bc_cell.size());
+    for (size_t k = 0; k < br.size(); ++k) {
+      br[k] = y.xrow_of[c->g.bc_cell[k]];
+      if (br[k] < 0) return set_err(c, LBM_E_ARG, "internal: boundary cell without an exception row");
+    }
+    if ((s = upload(c, &c->d_bc_row, br.data(), br.size())) != LBM_OK) return s;
   }
   (void)NCH;
   c->d_counters = (unsigned long long *)dev_alloc(c, sizeof(unsigned long long) * CNT_COUNT * CNT_COPIES);

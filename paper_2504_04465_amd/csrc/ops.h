@@ -152,6 +152,16 @@ struct BArgs {
   FaceVals fv;
   PhysArgs ph;
   unsigned long long *counters;
+  // in-place streaming (mode 0: two buffers): the source cell's
+  // post-collision populations are in its own rows opp(i) (mode 1, odd
+  // phase) or in its staging slot stage[src] (mode 2, even phase); the
+  // boundary cell's populations are written as its own store would leave
+  // them: rows opp(i) (mode 1), or pushed through its exception row
+  // bc_row[k] (mode 2)
+  int mode;
+  const int32_t *stage, *bc_row;
+  const int32_t *xnbr;
+  int64_t xstride;
 };
 
 // gathers of the synchronisation-point state: moments, populations, sums

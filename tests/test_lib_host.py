@@ -149,17 +149,16 @@ def test_brick_layout_uniform_periodic_needs_no_rows():
 
 
 def test_in_place_streaming_limits():
-    """in-place streaming is refused for open faces (boundary layers and
-    sponges would need their fills in both phases) and accepted on refined
-    grids with periodic, wall and moving-wall faces"""
+    """in-place streaming is accepted on refined grids with any faces
+    (boundary layers are filled in the level's phase) and refused for the
+    multiplier surrogate"""
     w = W.shear(n=16, levels=2, lattice="D2Q9", collision="RR")
     s = B.LBM.from_workload(w, host_only=True, in_place=True)
     assert s.n_levels == 2
-    with pytest.raises(B.LbmError) as e:
-        B.LBM.from_workload(W.cylinder(scale=16, steps=1), host_only=True, in_place=True)
-    assert e.value.code == -7
-    w = W.cavity(n=16, levels=1)
-    w.faces[0] = W.Face("neumann")
+    s = B.LBM.from_workload(W.cylinder(scale=16, steps=1), host_only=True, in_place=True)
+    assert s.n_levels == 4
+    w = W.airfoil(scale=16, steps=1)
+    w.collision = "DDF_MLP"
     with pytest.raises(B.LbmError) as e:
         B.LBM.from_workload(w, host_only=True, in_place=True)
     assert e.value.code == -7
