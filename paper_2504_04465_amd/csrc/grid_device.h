@@ -26,7 +26,8 @@ struct DevAlloc {
 // Canonical tables the caller keeps on the device (allocated through the
 // DevAlloc, owned by the caller): the coordinates and the neighbour list are
 // then not copied into the HostGrid (its xyz and nbr stay empty; fetch them
-// with fetch_host_mirror when a host reader needs them).
+// with fetch_host_mirror when a host reader needs them).  The caller may
+// release nbr once it has formed the per-slot flags.
 struct DeviceGridArrays {
   int32_t *xyz = nullptr;     // [n][3]
   int8_t *lev = nullptr;      // [n]
@@ -46,7 +47,8 @@ int build_grid_device(const LatticeInfo &lat, int dim, const int32_t ext[3], int
                       const MaskView *solid, const FaceSpec faces[6], const bool periodic[3], const DevAlloc &da,
                       hipStream_t stream, HostGrid *g, DeviceLayout *y, DeviceGridArrays *keep, std::string *err);
 
-// g->xyz and g->nbr from the kept device tables (no-op when present).
+// g->xyz and g->nbr from the kept device tables, where kept and not yet on
+// the host.
 int fetch_host_mirror(const DeviceGridArrays &dg, HostGrid *g, hipStream_t stream, std::string *err);
 
 // per-slot device flags: the canonical flag, F_MOVING where a population is

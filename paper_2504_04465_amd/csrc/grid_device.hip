@@ -80,6 +80,11 @@ inline unsigned grid_for(int64_t n) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 1 << 20));
 }
 
+// for kernels that end in a few atomics on one shared word per wavefront
+// (bounding boxes): a grid of at most 2048 blocks, each thread striding over
+// more cells, keeps those atomics from queueing behind each other
+inline unsigned grid_few(int64_t n) { return std::min<unsigned>(grid_for(n), 2048u); }
+
 #define GRID_STRIDE(i, n) \
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
@@ -1124,7 +1129,7 @@ int build_grid_device(const LatticeInfo &lat, int dim, const int32_t ext_in[3], 
     if (m == 0) continue;
     const int init[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
     DEV_TRY(hipMemcpyAsync(bbox, init, sizeof init, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_brick_start, dim3(grid_for(m)), dim3(T), 0, st, c0, m, D, sh, xyz, fl, bbox);
+    hipLaunchKernelGGL(k_brick_start, dim3(grid_few(m)), dim3(T), 0, st, c0, m, D, sh, xyz, fl, bbox);
     int64_t nb = 0;
     DEV_TRY(exclusive_sum(pool, fl, pos, m, st, &nb));
     int hb[6];
@@ -1239,10 +1244,16 @@ int build_grid_device(const LatticeInfo &lat, int dim, const int32_t ext_in[3], 
 }
 
 int fetch_host_mirror(const DeviceGridArrays &dg, HostGrid *g, hipStream_t st, std::string *err) {
-  if (!dg.xyz || (!g->xyz.empty() && !g->nbr.empty())) return 0;
-  if (g->xyz.empty()) DEV_TRY(down(g->xyz, dg.xyz, 3 * dg.n, st));
-  if (g->nbr.empty()) DEV_TRY(down(g->nbr, dg.nbr, (size_t)dg.Qm * dg.n, st));
-  DEV_TRY(hipStreamSynchronize(st));
+  bool any = false;
+  if (dg.xyz && g->xyz.empty()) {
+    DEV_TRY(down(g->xyz, dg.xyz, 3 * dg.n, st));
+    any = true;
+  }
+  if (dg.nbr && g->nbr.empty()) {
+    DEV_TRY(down(g->nbr, dg.nbr, (size_t)dg.Qm * dg.n, st));
+    any = true;
+  }
+  if (any) DEV_TRY(hipStreamSynchronize(st));
   return 0;
 }
 
@@ -1294,7 +1305,7 @@ int remesh_sources_device(const HostGrid &old, const DeviceGridArrays &dold, con
   for (int l = 0; l < L; ++l) {
     const int64_t m = old.off[l + 1] - old.off[l];
     if (m > 0)
-      hipLaunchKernelGGL(k_flow_bbox, dim3(grid_for(m)), dim3(T), 0, st, old.off[l], m, oxyz, oflag, bbox + 6 * l);
+      hipLaunchKernelGGL(k_flow_bbox, dim3(grid_few(m)), dim3(T), 0, st, old.off[l], m, oxyz, oflag, bbox + 6 * l);
   }
   DEV_TRY(hipMemcpyAsync(hb.data(), bbox, sizeof(int) * hb.size(), hipMemcpyDeviceToHost, st));
   DEV_TRY(hipStreamSynchronize(st));

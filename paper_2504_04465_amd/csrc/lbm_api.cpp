@@ -46,6 +46,18 @@ struct lbm_ctx {
   int32_t *d_bc_row = nullptr; // in place: exception row of each boundary-layer cell
   DeviceGridArrays dg;         // canonical tables kept on the device by the device grid build
   std::vector<int32_t> stage;  // in place: slot -> staging slot (coarse ghosts, boundary sources), or -1
+  // the last device build's inputs: the canonical neighbour list is not
+  // kept on the device (the bulk pulls do not use it); an export of it
+  // builds the grid again
+  struct BuildInputs {
+    int dim = 0, L = 0;
+    int32_t ext[3] = {1, 1, 1};
+    std::vector<std::vector<uint8_t>> rdata, sdata;
+    std::vector<MaskView> rv, sv;
+    bool has_solid = false;
+    FaceSpec fs[6];
+    bool periodic[3] = {false, false, false};
+  } bi;
   HostGrid g;
   DeviceLayout lay;
   lbm_face_bc face[6]{};
@@ -614,6 +626,27 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
   const bool on_device = c->device_build && !c->p.host_only;
   if (on_device) {
     // the tree and its layout built on the GPU, copied into c->g / c->lay
+    auto &bi = c->bi;
+    bi.dim = dim;
+    bi.L = n_levels;
+    for (int a = 0; a < 3; ++a) bi.ext[a] = ext[a];
+    bi.rdata.assign(rv.size(), {});
+    bi.sdata.assign(sv.size(), {});
+    bi.rv = rv;
+    bi.sv = sv;
+    bi.has_solid = solid != nullptr;
+    for (size_t l = 0; l < rv.size(); ++l)
+      if (rv[l].data) {
+        bi.rdata[l].assign(rv[l].data, rv[l].data + (size_t)rv[l].n[0] * rv[l].n[1] * rv[l].n[2]);
+        bi.rv[l].data = bi.rdata[l].data();
+      }
+    for (size_t l = 0; l < sv.size(); ++l)
+      if (sv[l].data) {
+        bi.sdata[l].assign(sv[l].data, sv[l].data + (size_t)sv[l].n[0] * sv[l].n[1] * sv[l].n[2]);
+        bi.sv[l].data = bi.sdata[l].data();
+      }
+    for (int k = 0; k < 6; ++k) bi.fs[k] = fs[k];
+    for (int a = 0; a < 3; ++a) bi.periodic[a] = periodic[a];
     DevAlloc da{&build_alloc, &build_release, c};
     const int rc = build_grid_device(c->lat, dim, ext, n_levels, rv.data(), solid ? sv.data() : nullptr, fs,
                                      periodic, da, c->stream, &c->g, &c->lay, &c->dg, &err);
@@ -702,6 +735,8 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
     if (!c->d_flags) return set_err(c, LBM_E_NOMEM, "flag allocation failed");
     launch_slot_flags(c->dg, NS, c->d_flags, c->stream);
     if ((s = check_launch(c)) != LBM_OK) return s;
+    dev_release(c, c->dg.nbr);  // (Q-1) x 4 B per cell the update never reads
+    c->dg.nbr = nullptr;
   } else {
     // device flags per slot: the canonical ones, F_MOVING where a population
     // is pulled from a moving wall, F_HOLE for slots without a cell
@@ -828,9 +863,21 @@ lbm_status lbm_grid_export(lbm_ctx *c, int32_t *coords, int8_t *level, uint8_t *
   const int64_t n = c->N;
   const int Qm = c->lat.Q - 1;
   if (coords || nbr) {
-    // a device-built grid keeps its coordinates and neighbour list there
+    // a device-built grid keeps its coordinates on the device, and not its
+    // canonical neighbour list: that comes from building the grid again
     std::string err;
     if (fetch_host_mirror(c->dg, &c->g, c->stream, &err) != 0) return set_err(c, LBM_E_DEVICE, err);
+    if (nbr && c->g.nbr.empty()) {
+      const auto &bi = c->bi;
+      HostGrid tg;
+      DeviceLayout ty;
+      DevAlloc da{&build_alloc, &build_release, c};
+      if (build_grid_device(c->lat, bi.dim, bi.ext, bi.L, bi.rv.data(), bi.has_solid ? bi.sv.data() : nullptr, bi.fs,
+                            bi.periodic, da, c->stream, &tg, &ty, nullptr, &err) != 0 ||
+          tg.n != c->g.n)
+        return set_err(c, LBM_E_DEVICE, "neighbour list rebuild: " + err);
+      c->g.nbr = std::move(tg.nbr);
+    }
   }
   if (coords) memcpy(coords, c->g.xyz.data(), sizeof(int32_t) * 3 * n);
   if (level) memcpy(level, c->g.lev.data(), n);
