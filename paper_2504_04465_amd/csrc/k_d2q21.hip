@@ -33,18 +33,17 @@ __global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
   const int32_t brick = stage_bricks<L, S>(a.topo, nbs, c, live);
   const uint8_t fl = live ? a.flags[c] : (uint8_t)F_HOLE;
   const bool valid = !(fl & F_HOLE);
-  const int64_t stride = a.stride;
   C rho = (C)1, u[3] = {(C)0, (C)0, (C)0}, T = (C)1;
   if (valid) {
     C f[Q], g[Q];
-    gather<L, S, PRE, true, 0, false>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[w], stride, a.vbase, c, l, brick,
+    gather<L, S, PRE, true, 0, false>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[w], a.vbase, c, l, brick,
                             a.topo.xmask[brick], a.ph.uw, a.ph.cs2w, f, g);
     cell_moments<L, C, true>(f, g, (C)a.ph.Cv, rho, u, T);
   }
   // the populations again, after the equilibrium (no code motion across)
   auto pull = [&](C *f, C *g) {
     asm volatile("" ::: "memory");
-    gather<L, S, PRE, true, 0, false>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[w], stride, a.vbase, c, l, brick,
+    gather<L, S, PRE, true, 0, false>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[w], a.vbase, c, l, brick,
                             a.topo.xmask[brick], a.ph.uw, a.ph.cs2w, f, g);
   };
   const bool collide = valid && !(fl & (F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ));
@@ -110,8 +109,8 @@ __global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
     S *gout = (S *)a.gout;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      Sto<S>::stn(fout, (int64_t)i * stride + c, f[i] - om * (f[i] - feq[i]), L::S.w[i]);
-      Sto<S>::stn(gout, (int64_t)i * stride + c, g[i] - om * (g[i] - geq[i]), 0.0);
+      Sto<S>::stn(fout, pix<Q>(i, c), f[i] - om * (f[i] - feq[i]), L::S.w[i]);
+      Sto<S>::stn(gout, pix<Q>(i, c), g[i] - om * (g[i] - geq[i]), 0.0);
     }
   } else if (valid) {
     // fine ghosts and boundary layers: streamed, not collided
@@ -121,8 +120,8 @@ __global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
     S *gout = (S *)a.gout;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      Sto<S>::stn(fout, (int64_t)i * stride + c, f[i], L::S.w[i]);
-      Sto<S>::stn(gout, (int64_t)i * stride + c, g[i], 0.0);
+      Sto<S>::stn(fout, pix<Q>(i, c), f[i], L::S.w[i]);
+      Sto<S>::stn(gout, pix<Q>(i, c), g[i], 0.0);
     }
   }
 }

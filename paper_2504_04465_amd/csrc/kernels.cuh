@@ -1,10 +1,11 @@
 // kernels.cuh -- HIP kernels of the refined-grid lattice Boltzmann update for
 // gfx950, templated on lattice, collision model and population storage.
 //
-// Data layout (HBM): populations are structure-of-arrays, f[i * stride + c],
-// double buffered per level; each level's newest buffer holds post-collision
-// populations (the pull of the next update streams them).  The pull source
-// of population i of cell c is nbr[(i-1) * stride + c]:
+// Data layout (HBM): populations in chunks of 4096 slots, each chunk the Q
+// rows of its slots one after the other (f[pix<Q>(i, c)]), double buffered
+// per level; each level's newest buffer holds post-collision populations
+// (the pull of the next update streams them).  The pull source of
+// population i of cell c is nbr[(i-1) * stride + c]:
 //   >= vbase : a coalesced slot of a coarse ghost (unknown population),
 //   >= 0     : a cell of the same level (the cell itself when the paper's
 //              rule keeps the own value),
@@ -147,6 +148,20 @@ struct Brick {
   static constexpr int NBP = L::D == 3 ? 32 : 16;
 };
 
+// element of population i of slot s (the chunked layout of the buffers)
+template <int Q>
+__device__ inline int64_t pix(int64_t i, int64_t s) {
+  return (((s >> PCH_SH) * Q + i) << PCH_SH) + (s & (PCH - 1));
+}
+
+// offset of brick b's population-0 row in units of 64 values (32 bits for
+// any buffer of fewer than 2^38 / Q slots)
+template <int Q>
+__device__ inline uint32_t brick_unit(int32_t b) {
+  constexpr int BPC = (int)(PCH >> 6);  // bricks per chunk
+  return (uint32_t)(b / BPC) * (uint32_t)(Q * BPC) + (uint32_t)(b % BPC);
+}
+
 // coordinate d of lane inside its brick
 template <class L>
 __device__ inline int lane_coord(int lane, int d) {
@@ -176,7 +191,7 @@ __device__ inline int lane_bits(int p, int d) {
 // the moving-wall term is the same in that representation.
 template <class L, class S, bool PRE, bool DDF, int AA = 0, bool NZ = true, bool RAW = false>
 __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnbr, int64_t xstride, int64_t row,
-                                  int64_t stride, int64_t vbase, int64_t c, const double (&uw)[6][3], double cs2w,
+                                  int64_t vbase, int64_t c, const double (&uw)[6][3], double cs2w,
                                   typename Sto<S>::C *f, typename Sto<S>::C *g, uint64_t want = ~0ull,
                                   const double *xdu = nullptr) {
   using C = typename Sto<S>::C;
@@ -189,8 +204,8 @@ __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnb
     const int32_t s = sv[i];
     int64_t idx;
     const int ri = AA == 2 ? L::S.opp[i] : i, ro = AA == 2 ? i : L::S.opp[i];
-    if (PRE) idx = (int64_t)i * stride + ((int64_t)s >= vbase ? (int64_t)s : c);
-    else idx = s >= 0 ? (int64_t)ri * stride + s : (int64_t)ro * stride + c;
+    if (PRE) idx = pix<L::Q>(i, (int64_t)s >= vbase ? (int64_t)s : c);
+    else idx = s >= 0 ? pix<L::Q>(ri, s) : pix<L::Q>(ro, c);
     // the lattice is symmetric: w of the opposite population is w_i
     f[i] = RAW ? Sto<S>::ldr(fin[idx]) : Sto<S>::ld(fin, idx, L::S.w[i]);
     if (DDF) g[i] = Sto<S>::ld(gin, idx, 0.0);
@@ -209,29 +224,29 @@ __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnb
 // Bulk lanes: the source of population i sits in the brick at offset
 // dir = sum_d w_d 3^d (w_d = 0, 1, 2 for a step to the lower neighbour, none,
 // the upper neighbour along d) at local coordinates (lc - xi_i) mod BS.  The
-// byte offset of every neighbour brick is staged in LDS (nbs); per lane and
-// axis the table K[d][xi_d] packs (LDS byte offset of the direction part) << 16
-// | (byte offset of the local coordinate part), so a population costs two
-// integer adds, an LDS read and a load with a 32-bit offset from the
-// population's base address.
+// offset of every neighbour brick (brick_unit) is staged in LDS (nbs); per
+// lane and axis the table K[d][xi_d] packs (LDS byte offset of the direction
+// part) << 16 | (byte offset of the local coordinate part), so a population
+// costs two integer adds, an LDS read, a multiply-add and a load from the
+// population's row base.
 //
 // Lanes flagged in the brick's exception mask read their explicit row:
 // every source is loaded before any is used, so the loads overlap.
 template <class L, class S, bool PRE, bool DDF, int AA = 0, bool NZ = true, bool RAW = false>
-__device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const uint32_t *nbs, int64_t stride,
-                              int64_t vbase, int64_t c, int lane, int32_t brick, uint64_t xm,
+__device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const uint32_t *nbs, int64_t vbase, int64_t c, int lane, int32_t brick, uint64_t xm,
                               const double (&uw)[6][3], double cs2w, typename Sto<S>::C *f,
                               typename Sto<S>::C *g) {
   using C = typename Sto<S>::C;
   constexpr int BS = Brick<L>::BS, R = L::B, D = L::D;
-  f[0] = RAW ? Sto<S>::ldr(fin[c]) : Sto<S>::ld(fin, c, L::S.w[0]);
-  if (DDF) g[0] = Sto<S>::ld(gin, c, 0.0);
+  const int64_t c0 = pix<L::Q>(0, c);
+  f[0] = RAW ? Sto<S>::ldr(fin[c0]) : Sto<S>::ld(fin, c0, L::S.w[0]);
+  if (DDF) g[0] = Sto<S>::ld(gin, c0, 0.0);
   if (!((xm >> lane) & 1ull)) {
     if (PRE) {
 #pragma unroll
       for (int i = 1; i < L::Q; ++i) {
-        f[i] = RAW ? Sto<S>::ldr(fin[(int64_t)i * stride + c]) : Sto<S>::ld(fin, (int64_t)i * stride + c, L::S.w[i]);
-        if (DDF) g[i] = Sto<S>::ld(gin, (int64_t)i * stride + c, 0.0);
+        f[i] = RAW ? Sto<S>::ldr(fin[c0 + i * PCH]) : Sto<S>::ld(fin, c0 + i * PCH, L::S.w[i]);
+        if (DDF) g[i] = Sto<S>::ld(gin, c0 + i * PCH, 0.0);
       }
       return;
     }
@@ -253,19 +268,25 @@ __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const 
     }
     const char *fb = (const char *)fin;
     const char *gb = (const char *)gin;
-    const int64_t pstride = stride * (int64_t)sizeof(S);
+    constexpr int64_t rbytes = PCH * (int64_t)sizeof(S);
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
       const uint32_t k = K[0][cx_<L>(i, 0) + R] + K[1][cx_<L>(i, 1) + R] + K[2][cx_<L>(i, 2) + R];
-      const uint32_t off = nbs[k >> 18] + (k & 0xffffu);
+      const uint64_t off = (uint64_t)nbs[k >> 18] * (64u * sizeof(S)) + (k & 0xffffu);
       const int64_t ri = AA == 2 ? L::S.opp[i] : i;
-      const S v = *(const S *)(fb + ri * pstride + off);
+      const char *row = fb + ri * rbytes;
+      asm("" : "+s"(row));  // the uniform row base stays in SGPRs: one 64-bit add per lane
+      const S v = *(const S *)(row + off);
       f[i] = RAW ? Sto<S>::ldr(v) : Sto<S>::ldv(v, L::S.w[i]);
-      if (DDF) g[i] = Sto<S>::ldv(*(const S *)(gb + ri * pstride + off), 0.0);
+      if (DDF) {
+        const char *grow = gb + ri * rbytes;
+        asm("" : "+s"(grow));
+        g[i] = Sto<S>::ldv(*(const S *)(grow + off), 0.0);
+      }
     }
   } else {
     const int64_t row = tp.xbase[brick] + __popcll(xm & ((1ull << lane) - 1ull));
-    gather_row<L, S, PRE, DDF, AA, NZ, RAW>(fin, gin, tp.xnbr, tp.xstride, row, stride, vbase, c, uw, cs2w, f, g,
+    gather_row<L, S, PRE, DDF, AA, NZ, RAW>(fin, gin, tp.xnbr, tp.xstride, row, vbase, c, uw, cs2w, f, g,
                                             ~0ull, tp.xdu);
   }
 }
@@ -276,13 +297,13 @@ __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const 
 // population opp(i) (the bounce-back the next pull would have applied).
 // RAW: f holds f_i - w_i (FP16 storage), stored as it is.
 template <class L, class S, bool DDF, bool RAW = false>
-__device__ inline void push_store(S *fout, S *gout, const Topo &tp, const uint32_t *nbs, int64_t stride, int64_t c,
+__device__ inline void push_store(S *fout, S *gout, const Topo &tp, const uint32_t *nbs, int64_t c,
                                   int lane, int32_t brick, uint64_t xm, const double (&uw)[6][3], double cs2w,
                                   const typename Sto<S>::C *f, const typename Sto<S>::C *g) {
   using C = typename Sto<S>::C;
   constexpr int BS = Brick<L>::BS, R = L::B, D = L::D;
-  Sto<S>::stn(fout, c, f[0], RAW ? 0.0 : L::S.w[0]);
-  if (DDF) Sto<S>::stn(gout, c, g[0], 0.0);
+  Sto<S>::stn(fout, pix<L::Q>(0, c), f[0], RAW ? 0.0 : L::S.w[0]);
+  if (DDF) Sto<S>::stn(gout, pix<L::Q>(0, c), g[0], 0.0);
   if (!((xm >> lane) & 1ull)) {
     uint32_t K[3][2 * R + 1];
 #pragma unroll
@@ -302,15 +323,21 @@ __device__ inline void push_store(S *fout, S *gout, const Topo &tp, const uint32
     }
     char *fb = (char *)fout;
     char *gb = (char *)gout;
-    const int64_t pstride = stride * (int64_t)sizeof(S);
+    constexpr int64_t rbytes = PCH * (int64_t)sizeof(S);
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
       // x + xi_i is the pull source of the opposite population
       const int j = L::S.opp[i];
       const uint32_t k = K[0][cx_<L>(j, 0) + R] + K[1][cx_<L>(j, 1) + R] + K[2][cx_<L>(j, 2) + R];
-      const uint32_t off = nbs[k >> 18] + (k & 0xffffu);
-      Sto<S>::stn((S *)(fb + i * pstride + off), 0, f[i], RAW ? 0.0 : L::S.w[i]);
-      if (DDF) Sto<S>::stn((S *)(gb + i * pstride + off), 0, g[i], 0.0);
+      const uint64_t off = (uint64_t)nbs[k >> 18] * (64u * sizeof(S)) + (k & 0xffffu);
+      char *row = fb + i * rbytes;
+      asm("" : "+s"(row));  // uniform row base in SGPRs
+      Sto<S>::stn((S *)(row + off), 0, f[i], RAW ? 0.0 : L::S.w[i]);
+      if (DDF) {
+        char *grow = gb + i * rbytes;
+        asm("" : "+s"(grow));
+        Sto<S>::stn((S *)(grow + off), 0, g[i], 0.0);
+      }
     }
   } else {
     const int64_t row = tp.xbase[brick] + __popcll(xm & ((1ull << lane) - 1ull));
@@ -322,19 +349,19 @@ __device__ inline void push_store(S *fout, S *gout, const Topo &tp, const uint32
       // its level keeps it) is stored in its own row; nobody pulls from a
       // cell's own slot through the opposite link, so that push is dropped
       if (tp.xnbr[(int64_t)(i - 1) * tp.xstride + row] == (int32_t)c) {
-        Sto<S>::stn(fout, (int64_t)i * stride + c, f[i], RAW ? 0.0 : L::S.w[i]);
-        if (DDF) Sto<S>::stn(gout, (int64_t)i * stride + c, g[i], 0.0);
+        Sto<S>::stn(fout, pix<L::Q>(i, c), f[i], RAW ? 0.0 : L::S.w[i]);
+        if (DDF) Sto<S>::stn(gout, pix<L::Q>(i, c), g[i], 0.0);
       }
       if (s == (int32_t)c) continue;
       if (s >= 0) {
-        Sto<S>::stn(fout, (int64_t)i * stride + s, f[i], RAW ? 0.0 : L::S.w[i]);
-        if (DDF) Sto<S>::stn(gout, (int64_t)i * stride + s, g[i], 0.0);
+        Sto<S>::stn(fout, pix<L::Q>(i, s), f[i], RAW ? 0.0 : L::S.w[i]);
+        if (DDF) Sto<S>::stn(gout, pix<L::Q>(i, s), g[i], 0.0);
       } else {
         C v = f[i];
         if (s <= -2)
           v += (C)(2.0 * L::S.w[j] * wall_dot<L>(uw, -2 - s, j) / cs2w);  // no inflow noise in place
-        Sto<S>::stn(fout, (int64_t)j * stride + c, v, RAW ? 0.0 : L::S.w[j]);
-        if (DDF) Sto<S>::stn(gout, (int64_t)j * stride + c, g[i], 0.0);
+        Sto<S>::stn(fout, pix<L::Q>(j, c), v, RAW ? 0.0 : L::S.w[j]);
+        if (DDF) Sto<S>::stn(gout, pix<L::Q>(j, c), g[i], 0.0);
       }
     }
   }
@@ -343,7 +370,7 @@ __device__ inline void push_store(S *fout, S *gout, const Topo &tp, const uint32
 // Gather for one cell anywhere (no brick per wavefront): the neighbour
 // brick ids come straight from the table.  Used by the sampled read-back.
 template <class L, class S, bool PRE, bool DDF, int AA = 0>
-__device__ inline void gather_one(const S *fin, const S *gin, const Topo &tp, int64_t stride, int64_t vbase,
+__device__ inline void gather_one(const S *fin, const S *gin, const Topo &tp, int64_t vbase,
                                   int64_t c, const double (&uw)[6][3], double cs2w, typename Sto<S>::C *f,
                                   typename Sto<S>::C *g) {
   constexpr int BS = Brick<L>::BS;
@@ -351,11 +378,11 @@ __device__ inline void gather_one(const S *fin, const S *gin, const Topo &tp, in
   const int lane = (int)(c & 63);
   const uint64_t xm = tp.xmask[brick];
   if ((xm >> lane) & 1ull) {
-    gather<L, S, PRE, DDF, AA>(fin, gin, tp, nullptr, stride, vbase, c, lane, (int32_t)brick, xm, uw, cs2w, f, g);
+    gather<L, S, PRE, DDF, AA>(fin, gin, tp, nullptr, vbase, c, lane, (int32_t)brick, xm, uw, cs2w, f, g);
     return;
   }
-  f[0] = Sto<S>::ld(fin, c, L::S.w[0]);
-  if (DDF) g[0] = Sto<S>::ld(gin, c, 0.0);
+  f[0] = Sto<S>::ld(fin, pix<L::Q>(0, c), L::S.w[0]);
+  if (DDF) g[0] = Sto<S>::ld(gin, pix<L::Q>(0, c), 0.0);
 #pragma unroll
   for (int i = 1; i < L::Q; ++i) {
     int64_t src = c;
@@ -372,13 +399,13 @@ __device__ inline void gather_one(const S *fin, const S *gin, const Topo &tp, in
       src = (int64_t)tp.nbrick[brick * Brick<L>::NBP + dir] * 64 + loc;
     }
     const int64_t ri = AA == 2 ? L::S.opp[i] : i;
-    f[i] = Sto<S>::ld(fin, ri * stride + src, L::S.w[i]);
-    if (DDF) g[i] = Sto<S>::ld(gin, ri * stride + src, 0.0);
+    f[i] = Sto<S>::ld(fin, pix<L::Q>(ri, src), L::S.w[i]);
+    if (DDF) g[i] = Sto<S>::ld(gin, pix<L::Q>(ri, src), 0.0);
   }
 }
 
-// Per-block preamble of the kernels that gather: stages the byte offsets of
-// the neighbour bricks of the block's four bricks in LDS.  Every thread of
+// Per-block preamble of the kernels that gather: stages the offsets
+// (brick_unit) of the neighbour bricks of the block's bricks in LDS.  Every thread of
 // the block must call it.  Returns the wave-uniform brick id.
 template <class L, class S>
 __device__ inline int32_t stage_bricks(const Topo &tp, uint32_t (*nbs)[Brick<L>::NBP], int64_t c, bool live) {
@@ -386,7 +413,7 @@ __device__ inline int32_t stage_bricks(const Topo &tp, uint32_t (*nbs)[Brick<L>:
   const int32_t brick = __builtin_amdgcn_readfirstlane((int32_t)(c >> 6));
   if (live && lane < Brick<L>::NB) {
     const int32_t nb = tp.nbrick[(int64_t)brick * Brick<L>::NBP + lane];
-    nbs[w][lane] = nb < 0 ? 0u : (uint32_t)nb * (uint32_t)(64 * sizeof(S));
+    nbs[w][lane] = nb < 0 ? 0u : brick_unit<L::Q>(nb);
   }
   __syncthreads();
   return brick;
@@ -1124,11 +1151,16 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
   const int64_t t = blk * CB + threadIdx.x;
   const bool live = t < count;  // whole wavefronts
   const int64_t c = begin + (live ? t : 0);
+  // the cell's flags and its brick's exception mask do not depend on the
+  // staged table: issued before the barrier, their latency overlaps the
+  // table's instead of adding two round trips after it
+  const uint8_t fl = a.flags[c];
+  // (a vector load of the wavefront's one mask: a scalar load would be
+  // sunk past the barrier to its first use)
+  const uint64_t xm = a.topo.xmask[c >> 6];
   const int32_t brick = stage_bricks<L, S>(a.topo, nbs, c, live);
   if (!live) return;
-  const uint8_t fl = a.flags[c];
   if (fl & F_HOLE) return;
-  const int64_t stride = a.stride;
   const S *fin = (const S *)fin_p;
   const S *gin = (const S *)gin_p;
   C f[Q];
@@ -1138,8 +1170,7 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
   // and the moments and the regularised populations are formed from the
   // small deviations instead of from f_i ~ w_i
   constexpr bool SH = std::is_same<S, __half>::value && COLL == COLL_RR && product_basis<L>();
-  gather<L, S, PRE || AA == 1, DDF, AA == 2 ? 2 : 0, NZ, SH>(fin, gin, a.topo, nbs[threadIdx.x >> 6], stride,
-                                                       a.vbase, c, threadIdx.x & 63, brick, a.topo.xmask[brick],
+  gather<L, S, PRE || AA == 1, DDF, AA == 2 ? 2 : 0, NZ, SH>(fin, gin, a.topo, nbs[threadIdx.x >> 6], a.vbase, c, threadIdx.x & 63, brick, xm,
                                                        a.ph.uw, a.ph.cs2w, f, g);
   if (!(fl & (F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ))) {
     C rho, u[3], T = (C)0, rho1 = (C)0;
@@ -1187,7 +1218,7 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
       double lam[NLAM];
       if constexpr (COLL >= COLL_DDF_NEWTON) {
 #pragma unroll
-        for (int k = 0; k < NLAM; ++k) lam[k] = (double)((const LamT<S> *)a.lam)[(int64_t)k * stride + c];
+        for (int k = 0; k < NLAM; ++k) lam[k] = (double)((const LamT<S> *)a.lam)[(int64_t)k * a.stride + c];
       }
       int it;
       if constexpr (COLL >= COLL_DDF_NEWTON) {
@@ -1217,7 +1248,7 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
         else count_add(a.counters, CNT_NEWTON_ITERS, (unsigned long long)it);
         count_hist(a.counters, it);
 #pragma unroll
-        for (int k = 0; k < NLAM; ++k) ((LamT<S> *)a.lam)[(int64_t)k * stride + c] = (LamT<S>)lam[k];
+        for (int k = 0; k < NLAM; ++k) ((LamT<S> *)a.lam)[(int64_t)k * a.stride + c] = (LamT<S>)lam[k];
       }
       C te = (C)tau;
       if (a.ph.sensor_on) te *= sensor_alpha<L, C>(f, feq, te, (C)a.ph.sensor_A);
@@ -1240,27 +1271,29 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
       if (vs >= 0) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          Sto<S>::stn(fout, (int64_t)i * stride + vs, f[i], SH ? 0.0 : L::S.w[i]);
-          if (DDF) Sto<S>::stn(gout, (int64_t)i * stride + vs, g[i], 0.0);
+          Sto<S>::stn(fout, pix<Q>(i, vs), f[i], SH ? 0.0 : L::S.w[i]);
+          if (DDF) Sto<S>::stn(gout, pix<Q>(i, vs), g[i], 0.0);
         }
       }
     }
   }
   if constexpr (AA == 2) {
-    push_store<L, S, DDF, SH>(fout, gout, a.topo, nbs[threadIdx.x >> 6], stride, c, threadIdx.x & 63, brick,
-                          a.topo.xmask[brick], a.ph.uw, a.ph.cs2w, f, g);
+    push_store<L, S, DDF, SH>(fout, gout, a.topo, nbs[threadIdx.x >> 6], c, threadIdx.x & 63, brick,
+                          xm, a.ph.uw, a.ph.cs2w, f, g);
   } else {
-    // row base (uniform) + the cell's 32-bit byte offset: the address needs
-    // no per-lane 64-bit arithmetic (slots x bytes < 2^32 on every grid)
-    char *ob = (char *)fout;
-    char *gb = (char *)gout;
-    const int64_t pstride = stride * (int64_t)sizeof(S);
-    const uint32_t co = (uint32_t)c * (uint32_t)sizeof(S);
+    // row base (uniform: a wavefront's brick lies in one chunk) + the
+    // cell's 32-bit byte offset in the chunk: the address needs no per-lane
+    // 64-bit arithmetic
+    const int64_t ck = __builtin_amdgcn_readfirstlane((int32_t)(c >> PCH_SH));
+    constexpr int64_t rbytes = PCH * (int64_t)sizeof(S);
+    char *ob = (char *)fout + ck * Q * rbytes;
+    char *gb = DDF ? (char *)gout + ck * Q * rbytes : nullptr;
+    const uint32_t co = (uint32_t)(c & (PCH - 1)) * (uint32_t)sizeof(S);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int64_t r = AA == 1 ? L::S.opp[i] : i;
-      Sto<S>::stp((S *)(ob + r * pstride + co), f[i], SH ? 0.0 : L::S.w[i]);
-      if (DDF) Sto<S>::stp((S *)(gb + r * pstride + co), g[i], 0.0);
+      Sto<S>::stp((S *)(ob + r * rbytes + co), f[i], SH ? 0.0 : L::S.w[i]);
+      if (DDF) Sto<S>::stp((S *)(gb + r * rbytes + co), g[i], 0.0);
     }
   }
 }
@@ -1313,8 +1346,8 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
         const int32_t sv = a.xnbr[(int64_t)(i - 1) * a.xstride + crow];
         int64_t idx;
         const int64_t ri = AAF == 2 ? L::S.opp[i] : i, ro = AAF == 2 ? i : L::S.opp[i];
-        if (PRE) idx = (int64_t)i * a.stride + ((int64_t)sv >= a.vbase ? (int64_t)sv : (int64_t)ch);
-        else idx = sv >= 0 ? ri * a.stride + sv : ro * a.stride + ch;
+        if (PRE) idx = pix<L::Q>(i, (int64_t)sv >= a.vbase ? (int64_t)sv : (int64_t)ch);
+        else idx = sv >= 0 ? pix<L::Q>(ri, sv) : pix<L::Q>(ro, ch);
         v = Sto<S>::ld(fin, idx, L::S.w[i]);
         if (DDF) vg = Sto<S>::ld(gin, idx, 0.0);
         if (!PRE && sv <= -2)
@@ -1325,8 +1358,8 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
       if (DDF) vg = group_sum<NCH, C>(vg);
       if (lead && need) {
         const int64_t r = SW ? L::S.opp[i] : i;
-        Sto<S>::st(fout, r * a.stride + slot, v / nf, L::S.w[i]);
-        if (DDF) Sto<S>::st(gout, r * a.stride + slot, vg / nf, 0.0);
+        Sto<S>::st(fout, pix<L::Q>(r, slot), v / nf, L::S.w[i]);
+        if (DDF) Sto<S>::st(gout, pix<L::Q>(r, slot), vg / nf, 0.0);
       }
     }
   } else {
@@ -1334,7 +1367,7 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
     // (every child of a coarse ghost has an explicit row), all loads first
     C f[L::Q], g[DDF ? L::Q : 1];
     if (ch >= 0)
-      gather_row<L, S, PRE, DDF, AAF>(fin, gin, a.xnbr, a.xstride, crow, a.stride, a.vbase, ch, a.uw, a.cs2w, f, g,
+      gather_row<L, S, PRE, DDF, AAF>(fin, gin, a.xnbr, a.xstride, crow, a.vbase, ch, a.uw, a.cs2w, f, g,
                                       mask, a.xdu);
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
@@ -1345,8 +1378,8 @@ __global__ void __launch_bounds__(BLOCK) k_coalesce(const CArgs a) {
       if (DDF) vg = group_sum<NCH, C>(vg);
       if (lead && need) {
         const int64_t r = SW ? L::S.opp[i] : i;
-        Sto<S>::st(fout, r * a.stride + slot, v / nf, L::S.w[i]);
-        if (DDF) Sto<S>::st(gout, r * a.stride + slot, vg / nf, 0.0);
+        Sto<S>::st(fout, pix<L::Q>(r, slot), v / nf, L::S.w[i]);
+        if (DDF) Sto<S>::st(gout, pix<L::Q>(r, slot), vg / nf, 0.0);
       }
     }
   }
@@ -1388,40 +1421,40 @@ __global__ void __launch_bounds__(BLOCK) k_explode(const EArgs a) {
   S *fout = (S *)a.fout_fine;
   S v[L::Q], vg[DDF ? L::Q : 1];
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) v[i] = fin[(int64_t)i * a.stride + src];
+  for (int i = 0; i < L::Q; ++i) v[i] = fin[pix<L::Q>(i, src)];
   if (DDF)
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) vg[i] = ((const S *)a.gin_coarse)[(int64_t)i * a.stride + src];
+    for (int i = 0; i < L::Q; ++i) vg[i] = ((const S *)a.gin_coarse)[pix<L::Q>(i, src)];
   S *gout = (S *)a.gout_fine;
   if constexpr (MODE == 2) {
     const int64_t crow = a.crow[gk * NCH + (t % NCH)];
-    fout[ch] = v[0];
-    if (DDF) gout[ch] = vg[0];
+    fout[pix<L::Q>(0, ch)] = v[0];
+    if (DDF) gout[pix<L::Q>(0, ch)] = vg[0];
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
       const int j = L::S.opp[i];
       if (a.xnbr[(int64_t)(i - 1) * a.xstride + crow] == ch) {
-        fout[(int64_t)i * a.stride + ch] = v[i];
-        if (DDF) gout[(int64_t)i * a.stride + ch] = vg[i];
+        fout[pix<L::Q>(i, ch)] = v[i];
+        if (DDF) gout[pix<L::Q>(i, ch)] = vg[i];
       }
       const int32_t s = a.xnbr[(int64_t)(j - 1) * a.xstride + crow];
       if (s == ch) continue;
       if (s >= 0) {
-        fout[(int64_t)i * a.stride + s] = v[i];
-        if (DDF) gout[(int64_t)i * a.stride + s] = vg[i];
+        fout[pix<L::Q>(i, s)] = v[i];
+        if (DDF) gout[pix<L::Q>(i, s)] = vg[i];
       } else {
         C w = Sto<S>::ldv(v[i], L::S.w[i]);
         if (s <= -2) w += (C)(2.0 * L::S.w[j] * wall_dot<L>(a.uw, -2 - s, j) / a.cs2w);
-        Sto<S>::st(fout, (int64_t)j * a.stride + ch, w, L::S.w[j]);
-        if (DDF) gout[(int64_t)j * a.stride + ch] = vg[i];
+        Sto<S>::st(fout, pix<L::Q>(j, ch), w, L::S.w[j]);
+        if (DDF) gout[pix<L::Q>(j, ch)] = vg[i];
       }
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) fout[(int64_t)(MODE == 1 ? L::S.opp[i] : i) * a.stride + ch] = v[i];
+    for (int i = 0; i < L::Q; ++i) fout[pix<L::Q>(MODE == 1 ? L::S.opp[i] : i, ch)] = v[i];
     if (DDF)
 #pragma unroll
-      for (int i = 0; i < L::Q; ++i) gout[(int64_t)(MODE == 1 ? L::S.opp[i] : i) * a.stride + ch] = vg[i];
+      for (int i = 0; i < L::Q; ++i) gout[pix<L::Q>(MODE == 1 ? L::S.opp[i] : i, ch)] = vg[i];
   }
   if (LAM)
 #pragma unroll
@@ -1449,28 +1482,28 @@ __device__ inline T6 pick6(const T6 (&v)[6], int k) {
 // arithmetic applies.  G: the second distribution (stored without the
 // weight shift, bounced back without the moving-wall term).
 template <class L, class S, bool G = false>
-__device__ inline void push_value(S *f, int64_t stride, int64_t c, const int32_t *xnbr, int64_t xstride, int64_t row,
+__device__ inline void push_value(S *f, int64_t c, const int32_t *xnbr, int64_t xstride, int64_t row,
                                   int i, typename Sto<S>::C v, S raw, bool use_raw, const double (&uw)[6][3],
                                   double cs2w) {
   using C = typename Sto<S>::C;
   const int j = L::S.opp[i];
   const double wi = G ? 0.0 : L::S.w[i];
   if (xnbr[(int64_t)(i - 1) * xstride + row] == (int32_t)c) {
-    if (use_raw) f[(int64_t)i * stride + c] = raw;
-    else Sto<S>::st(f, (int64_t)i * stride + c, v, wi);
+    if (use_raw) f[pix<L::Q>(i, c)] = raw;
+    else Sto<S>::st(f, pix<L::Q>(i, c), v, wi);
   }
   const int32_t s = xnbr[(int64_t)(j - 1) * xstride + row];
   if (s == (int32_t)c) return;
   if (s >= 0) {
-    if (use_raw) f[(int64_t)i * stride + s] = raw;
-    else Sto<S>::st(f, (int64_t)i * stride + s, v, wi);
+    if (use_raw) f[pix<L::Q>(i, s)] = raw;
+    else Sto<S>::st(f, pix<L::Q>(i, s), v, wi);
   } else if (G) {
-    if (use_raw) f[(int64_t)j * stride + c] = raw;
-    else Sto<S>::st(f, (int64_t)j * stride + c, v, 0.0);
+    if (use_raw) f[pix<L::Q>(j, c)] = raw;
+    else Sto<S>::st(f, pix<L::Q>(j, c), v, 0.0);
   } else {
     C w = use_raw ? Sto<S>::ldv(raw, L::S.w[i]) : v;
     if (s <= -2) w += (C)(2.0 * L::S.w[j] * wall_dot<L>(uw, -2 - s, j) / cs2w);
-    Sto<S>::st(f, (int64_t)j * stride + c, w, L::S.w[j]);
+    Sto<S>::st(f, pix<L::Q>(j, c), w, L::S.w[j]);
   }
 }
 
@@ -1504,24 +1537,24 @@ __global__ void __launch_bounds__(BLOCK) k_bcfill(const BArgs a) {
   if (kind < 0) {  // Neumann: all loads, then all stores
     S v[L::Q], vg[DDF ? L::Q : 1];
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) v[i] = f[srow(i) * a.stride + sbase];
+    for (int i = 0; i < L::Q; ++i) v[i] = f[pix<L::Q>(srow(i), sbase)];
     if (DDF)
 #pragma unroll
-      for (int i = 0; i < L::Q; ++i) vg[i] = g[srow(i) * a.stride + sbase];
+      for (int i = 0; i < L::Q; ++i) vg[i] = g[pix<L::Q>(srow(i), sbase)];
     if constexpr (MODE == 2) {
-      f[c] = v[0];
-      if (DDF) g[c] = vg[0];
+      f[pix<L::Q>(0, c)] = v[0];
+      if (DDF) g[pix<L::Q>(0, c)] = vg[0];
 #pragma unroll
       for (int i = 1; i < L::Q; ++i) {
-        push_value<L, S>(f, a.stride, c, a.xnbr, a.xstride, row, i, (C)0, v[i], true, a.ph.uw, a.ph.cs2w);
-        if (DDF) push_value<L, S, true>(g, a.stride, c, a.xnbr, a.xstride, row, i, (C)0, vg[i], true, a.ph.uw, 1.0);
+        push_value<L, S>(f, c, a.xnbr, a.xstride, row, i, (C)0, v[i], true, a.ph.uw, a.ph.cs2w);
+        if (DDF) push_value<L, S, true>(g, c, a.xnbr, a.xstride, row, i, (C)0, vg[i], true, a.ph.uw, 1.0);
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < L::Q; ++i) f[srow(i) * a.stride + c] = v[i];
+      for (int i = 0; i < L::Q; ++i) f[pix<L::Q>(srow(i), c)] = v[i];
       if (DDF)
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) g[srow(i) * a.stride + c] = vg[i];
+        for (int i = 0; i < L::Q; ++i) g[pix<L::Q>(srow(i), c)] = vg[i];
     }
     if (LAM)
 #pragma unroll
@@ -1532,7 +1565,7 @@ __global__ void __launch_bounds__(BLOCK) k_bcfill(const BArgs a) {
   if (kind == 1) {
     rho = (C)0;
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) rho += Sto<S>::ld(f, srow(i) * a.stride + sbase, L::S.w[i]);
+    for (int i = 0; i < L::Q; ++i) rho += Sto<S>::ld(f, pix<L::Q>(srow(i), sbase), L::S.w[i]);
   }
   C u[3] = {(C)fu[0], (C)fu[1], (C)fu[2]};
   C feq[L::Q], geq[DDF ? L::Q : 1];
@@ -1547,18 +1580,18 @@ __global__ void __launch_bounds__(BLOCK) k_bcfill(const BArgs a) {
     for (int q = 0; q < NLAM; ++q) ((LamT<S> *)a.lam)[(int64_t)q * a.stride + c] = (LamT<S>)lam[q];
   }
   if constexpr (MODE == 2) {
-    Sto<S>::st(f, c, feq[0], L::S.w[0]);
-    if (DDF) Sto<S>::st(g, c, geq[0], 0.0);
+    Sto<S>::st(f, pix<L::Q>(0, c), feq[0], L::S.w[0]);
+    if (DDF) Sto<S>::st(g, pix<L::Q>(0, c), geq[0], 0.0);
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
-      push_value<L, S>(f, a.stride, c, a.xnbr, a.xstride, row, i, feq[i], S(), false, a.ph.uw, a.ph.cs2w);
-      if (DDF) push_value<L, S, true>(g, a.stride, c, a.xnbr, a.xstride, row, i, geq[i], S(), false, a.ph.uw, 1.0);
+      push_value<L, S>(f, c, a.xnbr, a.xstride, row, i, feq[i], S(), false, a.ph.uw, a.ph.cs2w);
+      if (DDF) push_value<L, S, true>(g, c, a.xnbr, a.xstride, row, i, geq[i], S(), false, a.ph.uw, 1.0);
     }
   } else {
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-      Sto<S>::st(f, srow(i) * a.stride + c, feq[i], L::S.w[i]);
-      if (DDF) Sto<S>::st(g, srow(i) * a.stride + c, geq[i], 0.0);
+      Sto<S>::st(f, pix<L::Q>(srow(i), c), feq[i], L::S.w[i]);
+      if (DDF) Sto<S>::st(g, pix<L::Q>(srow(i), c), geq[i], 0.0);
     }
   }
 }
@@ -1581,7 +1614,7 @@ __global__ void __launch_bounds__(BLOCK) k_gather(const MArgs a) {
     const int64_t c = a.slot_of[cell];
     C f[Q];
     C g[DDF ? Q : 1];
-    gather_one<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, a.stride, a.vbase, c, a.uw, a.cs2w,
+    gather_one<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, a.vbase, c, a.uw, a.cs2w,
                                    f, g);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -1601,7 +1634,7 @@ __global__ void __launch_bounds__(BLOCK) k_gather(const MArgs a) {
   C g[DDF ? Q : 1];
   const bool fine_ghost = valid && (a.flags[c] & F_FINE_GHOST);
   if (valid)
-    gather<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[threadIdx.x >> 6], a.stride,
+    gather<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[threadIdx.x >> 6],
                                a.vbase, c, threadIdx.x & 63, brick, a.topo.xmask[brick], a.uw, a.cs2w, f, g);
   if (a.mode == 0) {
     if (!valid) return;
@@ -1658,7 +1691,7 @@ __global__ void __launch_bounds__(BLOCK) k_sums(const MArgs a) {
     if (cell >= 0 && !(a.flags[c] & F_FINE_GHOST)) {
       C f[Q];
       C g[DDF ? Q : 1];
-      gather<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[threadIdx.x >> 6], a.stride,
+      gather<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[threadIdx.x >> 6],
                                  a.vbase, c, threadIdx.x & 63, brick, a.topo.xmask[brick], a.uw, a.cs2w, f, g);
       double q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -1713,8 +1746,8 @@ __global__ void __launch_bounds__(BLOCK) k_init(const IArgs a) {
   if (a.mode == 1) {
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-      Sto<S>::st(f, (int64_t)i * a.stride + c, (C)a.src[(int64_t)i * a.n + k0], L::S.w[i]);
-      if (DDF) Sto<S>::st(g, (int64_t)i * a.stride + c, (C)a.src_g[(int64_t)i * a.n + k0], 0.0);
+      Sto<S>::st(f, pix<L::Q>(i, c), (C)a.src[(int64_t)i * a.n + k0], L::S.w[i]);
+      if (DDF) Sto<S>::st(g, pix<L::Q>(i, c), (C)a.src_g[(int64_t)i * a.n + k0], 0.0);
     }
     if (LAM && a.src_lam)
       for (int k = 0; k < NLAM; ++k) ((LamT<S> *)a.lam)[(int64_t)k * a.stride + c] = (LamT<S>)a.src_lam[(int64_t)k * a.n + k0];
@@ -1734,8 +1767,8 @@ __global__ void __launch_bounds__(BLOCK) k_init(const IArgs a) {
   if (!(rho > (C)0) || !isfinite(rho)) count_add(a.counters, CNT_NONFINITE, 1);
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
-    Sto<S>::st(f, (int64_t)i * a.stride + c, feq[i], L::S.w[i]);
-    if (DDF) Sto<S>::st(g, (int64_t)i * a.stride + c, geq[i], 0.0);
+    Sto<S>::st(f, pix<L::Q>(i, c), feq[i], L::S.w[i]);
+    if (DDF) Sto<S>::st(g, pix<L::Q>(i, c), geq[i], 0.0);
   }
 }
 
@@ -1764,7 +1797,7 @@ __global__ void __launch_bounds__(BLOCK) k_sensor(const MArgs a, const PhysArgs 
   }
   C f[Q];
   C g[DDF ? Q : 1];
-  gather<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[threadIdx.x >> 6], a.stride, a.vbase,
+  gather<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[threadIdx.x >> 6], a.vbase,
                              c, threadIdx.x & 63, brick, a.topo.xmask[brick], a.uw, a.cs2w, f, g);
   C rho, u[3], T;
   cell_moments<L, C, DDF>(f, g, (C)a.Cv, rho, u, T);

@@ -679,7 +679,7 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
       if (c->stage[ss] < 0) c->stage[ss] = (int32_t)(c->NS + c->Ng + nstage++);
     }
   }
-  c->stride = ((c->NS + c->Ng + nstage + 63) / 64) * 64;
+  c->stride = ((c->NS + c->Ng + nstage + PCH - 1) / PCH) * PCH;  // whole population chunks
   {
     // bytes one update of level l must move at least: its populations in
     // and out (and multipliers), plus the level's share of the flag, brick
@@ -707,8 +707,8 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
   const size_t ssz = (size_t)c->ops.sizeof_storage;
   const DeviceLayout &y = c->lay;
   const int64_t N = c->N, NS = c->NS;
-  // bulk gathers address a population array with 32-bit byte offsets
-  if ((double)NS * (double)ssz >= 4294967296.0) return set_err(c, LBM_E_ARG, "grid too large for 32-bit offsets");
+  // bulk gathers stage each brick's offset in units of 64 values in 32 bits
+  if ((double)c->stride / 64.0 * Q >= 4294967296.0) return set_err(c, LBM_E_ARG, "grid too large for 32-bit brick offsets");
   for (int b = 0; b < 2; ++b) {
     if (b == 1 && c->p.in_place) {
       c->f[1] = c->f[0];
