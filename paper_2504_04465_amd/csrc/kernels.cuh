@@ -35,6 +35,19 @@ constexpr int BLOCK = 256;
 // read again before the level's next update, so it should not displace the
 // neighbour lines that other wavefronts still pull from the L2.
 // ---------------------------------------------------------------------------
+// pointers into global memory (address space 1): accesses through them are
+// global, not flat, instructions, which take an SGPR base plus a VGPR offset
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+
+// a storage value read through a global pointer (__half by its bits: its
+// class type has no constructor from that address space)
+template <class S>
+__device__ inline S gload(gptr<const char> p) {
+  if constexpr (std::is_same<S, __half>::value) return __ushort_as_half(*(gptr<const unsigned short>)p);
+  else return *(gptr<const S>)p;
+}
+
 template <class S>
 struct Sto;
 template <>
@@ -46,6 +59,7 @@ struct Sto<double> {
   __device__ static void st(double *p, int64_t k, C v, double) { p[k] = v; }
   __device__ static void stn(double *p, int64_t k, C v, double) { __builtin_nontemporal_store(v, p + k); }
   __device__ static void stp(double *p, C v, double) { __builtin_nontemporal_store(v, p); }
+  __device__ static void stg(gptr<double> p, C v, double) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct Sto<float> {
@@ -56,6 +70,7 @@ struct Sto<float> {
   __device__ static void st(float *p, int64_t k, C v, double) { p[k] = v; }
   __device__ static void stn(float *p, int64_t k, C v, double) { __builtin_nontemporal_store(v, p + k); }
   __device__ static void stp(float *p, C v, double) { __builtin_nontemporal_store(v, p); }
+  __device__ static void stg(gptr<float> p, C v, double) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct Sto<__half> {
@@ -81,6 +96,9 @@ struct Sto<__half> {
   }
   __device__ static void stp(__half *p, C v, double w) {
     __builtin_nontemporal_store(__half_as_ushort(cvt(v, w)), (unsigned short *)p);
+  }
+  __device__ static void stg(gptr<__half> p, C v, double w) {
+    __builtin_nontemporal_store(__half_as_ushort(cvt(v, w)), (gptr<unsigned short>)p);
   }
 };
 
@@ -232,7 +250,7 @@ __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnb
 //
 // Lanes flagged in the brick's exception mask read their explicit row:
 // every source is loaded before any is used, so the loads overlap.
-template <class L, class S, bool PRE, bool DDF, int AA = 0, bool NZ = true, bool RAW = false>
+template <class L, class S, bool PRE, bool DDF, int AA = 0, bool NZ = true, bool RAW = false, bool O32 = false>
 __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const uint32_t *nbs, int64_t vbase, int64_t c, int lane, int32_t brick, uint64_t xm,
                               const double (&uw)[6][3], double cs2w, typename Sto<S>::C *f,
                               typename Sto<S>::C *g) {
@@ -269,19 +287,24 @@ __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const 
     const char *fb = (const char *)fin;
     const char *gb = (const char *)gin;
     constexpr int64_t rbytes = PCH * (int64_t)sizeof(S);
+    // O32: the brick's byte offset fits 32 bits (a buffer under 4 GB) and
+    // is added to the uniform row base by the load itself
+    using OffT = std::conditional_t<O32, uint32_t, uint64_t>;
+    {
 #pragma unroll
-    for (int i = 1; i < L::Q; ++i) {
-      const uint32_t k = K[0][cx_<L>(i, 0) + R] + K[1][cx_<L>(i, 1) + R] + K[2][cx_<L>(i, 2) + R];
-      const uint64_t off = (uint64_t)nbs[k >> 18] * (64u * sizeof(S)) + (k & 0xffffu);
-      const int64_t ri = AA == 2 ? L::S.opp[i] : i;
-      const char *row = fb + ri * rbytes;
-      asm("" : "+s"(row));  // the uniform row base stays in SGPRs: one 64-bit add per lane
-      const S v = *(const S *)(row + off);
-      f[i] = RAW ? Sto<S>::ldr(v) : Sto<S>::ldv(v, L::S.w[i]);
-      if (DDF) {
-        const char *grow = gb + ri * rbytes;
-        asm("" : "+s"(grow));
-        g[i] = Sto<S>::ldv(*(const S *)(grow + off), 0.0);
+      for (int i = 1; i < L::Q; ++i) {
+        const uint32_t k = K[0][cx_<L>(i, 0) + R] + K[1][cx_<L>(i, 1) + R] + K[2][cx_<L>(i, 2) + R];
+        const OffT off = (OffT)nbs[k >> 18] * (OffT)(64u * sizeof(S)) + (OffT)(k & 0xffffu);
+        const int64_t ri = AA == 2 ? L::S.opp[i] : i;
+        auto row = (gptr<const char>)(fb + ri * rbytes);
+        asm("" : "+s"(row));  // the uniform row base stays in SGPRs
+        const S v = gload<S>(row + off);
+        f[i] = RAW ? Sto<S>::ldr(v) : Sto<S>::ldv(v, L::S.w[i]);
+        if (DDF) {
+          auto grow = (gptr<const char>)(gb + ri * rbytes);
+          asm("" : "+s"(grow));
+          g[i] = Sto<S>::ldv(gload<S>(grow + off), 0.0);
+        }
       }
     }
   } else {
@@ -324,19 +347,21 @@ __device__ inline void push_store(S *fout, S *gout, const Topo &tp, const uint32
     char *fb = (char *)fout;
     char *gb = (char *)gout;
     constexpr int64_t rbytes = PCH * (int64_t)sizeof(S);
+    {
 #pragma unroll
-    for (int i = 1; i < L::Q; ++i) {
-      // x + xi_i is the pull source of the opposite population
-      const int j = L::S.opp[i];
-      const uint32_t k = K[0][cx_<L>(j, 0) + R] + K[1][cx_<L>(j, 1) + R] + K[2][cx_<L>(j, 2) + R];
-      const uint64_t off = (uint64_t)nbs[k >> 18] * (64u * sizeof(S)) + (k & 0xffffu);
-      char *row = fb + i * rbytes;
-      asm("" : "+s"(row));  // uniform row base in SGPRs
-      Sto<S>::stn((S *)(row + off), 0, f[i], RAW ? 0.0 : L::S.w[i]);
-      if (DDF) {
-        char *grow = gb + i * rbytes;
-        asm("" : "+s"(grow));
-        Sto<S>::stn((S *)(grow + off), 0, g[i], 0.0);
+      for (int i = 1; i < L::Q; ++i) {
+        // x + xi_i is the pull source of the opposite population
+        const int j = L::S.opp[i];
+        const uint32_t k = K[0][cx_<L>(j, 0) + R] + K[1][cx_<L>(j, 1) + R] + K[2][cx_<L>(j, 2) + R];
+        const uint64_t off = (uint64_t)nbs[k >> 18] * (64u * sizeof(S)) + (k & 0xffffu);
+        auto row = (gptr<char>)(fb + i * rbytes);
+        asm("" : "+s"(row));  // uniform row base in SGPRs
+        Sto<S>::stg((gptr<S>)(row + off), f[i], RAW ? 0.0 : L::S.w[i]);
+        if (DDF) {
+          auto grow = (gptr<char>)(gb + i * rbytes);
+          asm("" : "+s"(grow));
+          Sto<S>::stg((gptr<S>)(grow + off), g[i], 0.0);
+        }
       }
     }
   } else {
@@ -1113,7 +1138,7 @@ struct CollideBlock {
 // XCD dispatch keeps its per-XCD contiguous order inside the level; a block
 // takes its level's buffers, cell range and relaxation time from the table
 // and runs the same update as a per-level launch.
-template <class L, int COLL, class S, bool PRE, int AA = 0, bool NZ = false>
+template <class L, int COLL, class S, bool PRE, int AA = 0, bool NZ = false, bool O32 = false>
 __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
     __attribute__((amdgpu_waves_per_eu(MinWaves<L, COLL, S>::value))) k_collide(const KArgs a) {
   using C = typename Sto<S>::C;
@@ -1170,7 +1195,7 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
   // and the moments and the regularised populations are formed from the
   // small deviations instead of from f_i ~ w_i
   constexpr bool SH = std::is_same<S, __half>::value && COLL == COLL_RR && product_basis<L>();
-  gather<L, S, PRE || AA == 1, DDF, AA == 2 ? 2 : 0, NZ, SH>(fin, gin, a.topo, nbs[threadIdx.x >> 6], a.vbase, c, threadIdx.x & 63, brick, xm,
+  gather<L, S, PRE || AA == 1, DDF, AA == 2 ? 2 : 0, NZ, SH, O32>(fin, gin, a.topo, nbs[threadIdx.x >> 6], a.vbase, c, threadIdx.x & 63, brick, xm,
                                                        a.ph.uw, a.ph.cs2w, f, g);
   if (!(fl & (F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ))) {
     C rho, u[3], T = (C)0, rho1 = (C)0;
@@ -1833,9 +1858,11 @@ struct Launch {
       // that the others keep their registers
       if constexpr (COLL < COLL_DDF_NEWTON) {
         if (pre) hipLaunchKernelGGL((k_collide<L, COLL, S, true, 0, true>), dim3(nb), dim3(CB), 0, s, a);
+        else if (a.topo.off32) hipLaunchKernelGGL((k_collide<L, COLL, S, false, 0, true, true>), dim3(nb), dim3(CB), 0, s, a);
         else hipLaunchKernelGGL((k_collide<L, COLL, S, false, 0, true>), dim3(nb), dim3(CB), 0, s, a);
       }
     } else if (pre) hipLaunchKernelGGL((k_collide<L, COLL, S, true>), dim3(nb), dim3(CB), 0, s, a);
+    else if (a.topo.off32) hipLaunchKernelGGL((k_collide<L, COLL, S, false, 0, false, true>), dim3(nb), dim3(CB), 0, s, a);
     else hipLaunchKernelGGL((k_collide<L, COLL, S, false>), dim3(nb), dim3(CB), 0, s, a);
   }
   static bool noisy(const KArgs &a) { return a.topo.xdu != nullptr; }
@@ -1844,7 +1871,9 @@ struct Launch {
       constexpr int CB = CollideBlock<L, COLL>::value;
       const dim3 grid((unsigned)a.multi.block0[a.multi.n]);
       if (a.multi.n > 0 && a.multi.block0[a.multi.n] > 0) {
-        if (noisy(a)) hipLaunchKernelGGL((k_collide<L, COLL, S, false, 0, true>), grid, dim3(CB), 0, s, a);
+        if (noisy(a) && a.topo.off32) hipLaunchKernelGGL((k_collide<L, COLL, S, false, 0, true, true>), grid, dim3(CB), 0, s, a);
+        else if (noisy(a)) hipLaunchKernelGGL((k_collide<L, COLL, S, false, 0, true>), grid, dim3(CB), 0, s, a);
+        else if (a.topo.off32) hipLaunchKernelGGL((k_collide<L, COLL, S, false, 0, false, true>), grid, dim3(CB), 0, s, a);
         else hipLaunchKernelGGL((k_collide<L, COLL, S, false>), grid, dim3(CB), 0, s, a);
       }
     }

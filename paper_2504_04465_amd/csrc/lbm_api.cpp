@@ -245,6 +245,7 @@ Topo topo(const lbm_ctx *c) {
   t.xnbr = c->d_xnbr;
   t.xstride = c->lay.xstride;
   t.xdu = c->d_xdu;
+  t.off32 = (double)c->ops.sizeof_storage * c->lat.Q * (double)c->stride < 4294967296.0;
   return t;
 }
 
@@ -1583,7 +1584,8 @@ lbm_status lbm_mlp_grad(lbm_ctx *c, const float *xh, const float *th, int64_t n,
   float *dx = (float *)tmp.take(sizeof(float) * 4 * n);
   float *dt = (float *)tmp.take(sizeof(float) * 8 * n);
   int32_t *dp = (int32_t *)tmp.take(sizeof(int32_t) * n);
-  if (!dx || !dt || !dp) return set_err(c, LBM_E_NOMEM, "gradient allocation failed");
+  float *gp = (float *)tmp.take(mlp_partials_bytes(n));
+  if (!dx || !dt || !dp || !gp) return set_err(c, LBM_E_NOMEM, "gradient allocation failed");
   std::vector<int32_t> perm(n);
   for (int64_t k = 0; k < n; ++k) perm[k] = (int32_t)k;
   HIP_TRY(c, hipMemcpyAsync(dx, xh, sizeof(float) * 4 * n, hipMemcpyHostToDevice, c->stream));
@@ -1591,7 +1593,7 @@ lbm_status lbm_mlp_grad(lbm_ctx *c, const float *xh, const float *th, int64_t n,
   HIP_TRY(c, hipMemcpyAsync(dp, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_mlp_g, 0, sizeof(float) * MLP_PARAMS, c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_mlp_loss, 0, sizeof(float), c->stream));
-  mlp_train_batch(c->d_mlp_ops, dx, dt, dp, 0, n, c->d_mlp_g, c->d_mlp_loss, c->stream);
+  mlp_train_batch(c->d_mlp_ops, dx, dt, dp, 0, n, gp, c->d_mlp_g, c->d_mlp_loss, c->stream);
   lbm_status s = check_launch(c);
   if (s != LBM_OK) return s;
   float lh = 0.0f;
@@ -1664,7 +1666,8 @@ lbm_status lbm_mlp_train(lbm_ctx *c, const double *x, const double *lambda, int6
   float *dx = (float *)tmp.take(sizeof(float) * 4 * n);
   float *dt = (float *)tmp.take(sizeof(float) * 8 * n);
   int32_t *dp = (int32_t *)tmp.take(sizeof(int32_t) * n);
-  if (!dx || !dt || !dp) return set_err(c, LBM_E_NOMEM, "training allocation failed");
+  float *gp = (float *)tmp.take(mlp_partials_bytes(batch));
+  if (!dx || !dt || !dp || !gp) return set_err(c, LBM_E_NOMEM, "training allocation failed");
   HIP_TRY(c, hipMemcpyAsync(dx, xh.data(), sizeof(float) * 4 * n, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(dt, th.data(), sizeof(float) * 8 * n, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_mlp_m, 0, sizeof(float) * MLP_PARAMS, c->stream));
@@ -1686,7 +1689,7 @@ lbm_status lbm_mlp_train(lbm_ctx *c, const double *x, const double *lambda, int6
       ++t;
       const double frac = (double)(t - 1) / (double)std::max<int64_t>(total, 1);
       const float lr_t = (float)(lr * (0.01 + 0.99 * 0.5 * (1.0 + std::cos(3.14159265358979323846 * frac))));
-      mlp_train_batch(c->d_mlp_ops, dx, dt, dp, b * batch, batch, c->d_mlp_g, c->d_mlp_loss, c->stream);
+      mlp_train_batch(c->d_mlp_ops, dx, dt, dp, b * batch, batch, gp, c->d_mlp_g, c->d_mlp_loss, c->stream);
       mlp_adam(c->d_mlp_w, c->d_mlp_m, c->d_mlp_v, c->d_mlp_g, c->d_mlp_ops, lr_t, t, c->stream);
     }
     if ((s = check_launch(c)) != LBM_OK) return s;

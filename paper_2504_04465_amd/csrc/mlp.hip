@@ -85,11 +85,16 @@ __global__ void k_mlp_adam(float *w, float *m, float *v, float *g, MlpOperands *
 }
 
 // ---------------------------------------------------------------------------
-// one 32-sample tile per wavefront: forward, loss, backward
+// one 32-sample tile per wavefront: forward, loss, backward.  Each block
+// writes its whole gradient (every trainable entry once) and its loss to a
+// slot of its own, gpart[block][MLP_NTRAIN] and lpart[block]; k_mlp_gsum
+// adds the slots in block order, so that training is reproducible run to
+// run (float atomics would add them in arrival order)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(64) k_mlp_train(const MlpOperands *P, const float *xh, const float *th,
                                                   const int32_t *perm, int64_t off, float inv_count,
-                                                  float *grad, float *loss) {
+                                                  float *gpart, float *lpart) {
+  float *grad = gpart + (int64_t)blockIdx.x * MLP_NTRAIN;
   __shared__ __align__(16) __bf16 xin[32 * 16];
   __shared__ __align__(16) __bf16 h1[32 * 64];
   __shared__ __align__(16) __bf16 h2[32 * 64];
@@ -130,7 +135,7 @@ __global__ void __launch_bounds__(64) k_mlp_train(const MlpOperands *P, const fl
   }
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) part += __shfl_xor(part, m, 64);
-  if (l == 0) atomicAdd(loss, part * inv_count);
+  if (l == 0) lpart[blockIdx.x] = part * inv_count;
   __syncthreads();
   const int kr = 8 * (l >> 5), lc = l & 31;
   // dW4 = d4^T h3 (rows: 8 outputs of 32, columns: 64 hidden), K = samples
@@ -153,13 +158,13 @@ __global__ void __launch_bounds__(64) k_mlp_train(const MlpOperands *P, const fl
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int m = c_row(l, r);
-      if (m < 8) atomicAdd(grad + MW4 + m * 64 + n0 + lc, acc[r]);
+      if (m < 8) grad[MW4 + m * 64 + n0 + lc] = acc[r];
     }
   }
   if (l < 8) {
     float s = 0.0f;
     for (int q = 0; q < 32; ++q) s += d4[q * 8 + l];
-    atomicAdd(grad + MB4 + l, s);
+    grad[MB4 + l] = s;
   }
   // delta3 = (d4 W4) .* silu'(z3)
 #pragma unroll
@@ -200,11 +205,11 @@ __global__ void __launch_bounds__(64) k_mlp_train(const MlpOperands *P, const fl
           acc = mfma32(a, b, acc);
         }
 #pragma unroll
-        for (int r = 0; r < 16; ++r) atomicAdd(grad + woff + (m0 + c_row(l, r)) * 64 + n0 + lc, acc[r]);
+        for (int r = 0; r < 16; ++r) grad[woff + (m0 + c_row(l, r)) * 64 + n0 + lc] = acc[r];
       }
     float s = 0.0f;
     for (int q = 0; q < 32; ++q) s += (float)dl[q * 64 + l];
-    atomicAdd(grad + boff + l, s);
+    grad[boff + l] = s;
   };
   grad_w(da, h2, MW3, MB3);
   // delta2 = (delta3 W3) .* silu'(z2)
@@ -248,14 +253,35 @@ __global__ void __launch_bounds__(64) k_mlp_train(const MlpOperands *P, const fl
       }
       acc = mfma32(a, b, acc);
     }
+    // columns lc and lc + 4 (the high and low parts of input lc) share
+    // the weight: their lanes (same rows) are added before the store
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
-      if (lc < 8) atomicAdd(grad + MW1 + (m0 + c_row(l, r)) * 4 + (lc & 3), acc[r]);
+    for (int r = 0; r < 16; ++r) {
+      const float v = acc[r] + __shfl_xor(acc[r], 4);
+      if (lc < 4) grad[MW1 + (m0 + c_row(l, r)) * 4 + lc] = v;
+    }
   }
   {
     float s = 0.0f;
     for (int q = 0; q < 32; ++q) s += (float)da[q * 64 + l];
-    atomicAdd(grad + MB1 + l, s);
+    grad[MB1 + l] = s;
+  }
+}
+
+// gradient of the batch = the blocks' slots added in block order; the
+// loss is accumulated (over the batches of an epoch)
+__global__ void __launch_bounds__(256) k_mlp_gsum(const float *gpart, const float *lpart, int nblk, float *grad,
+                                                  float *loss) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < MLP_NTRAIN) {
+    float s = 0.0f;
+    for (int b = 0; b < nblk; ++b) s += gpart[(int64_t)b * MLP_NTRAIN + i];
+    grad[i] = s;
+  }
+  if (i == 0) {
+    float s = 0.0f;
+    for (int b = 0; b < nblk; ++b) s += lpart[b];
+    *loss += s;
   }
 }
 
@@ -314,10 +340,15 @@ void mlp_operands(const float *w, void *P, hipStream_t st) {
 }
 
 void mlp_train_batch(const void *P, const float *xh, const float *th, const int32_t *perm, int64_t off,
-                     int64_t count, float *grad, float *loss, hipStream_t st) {
-  hipLaunchKernelGGL(k_mlp_train, dim3((unsigned)(count / 32)), dim3(64), 0, st, (const MlpOperands *)P, xh, th,
-                     perm, off, 1.0f / (float)(count * 8), grad, loss);
+                     int64_t count, float *gpart, float *grad, float *loss, hipStream_t st) {
+  const int nblk = (int)(count / 32);
+  float *lpart = gpart + (int64_t)nblk * MLP_NTRAIN;
+  hipLaunchKernelGGL(k_mlp_train, dim3((unsigned)nblk), dim3(64), 0, st, (const MlpOperands *)P, xh, th, perm, off,
+                     1.0f / (float)(count * 8), gpart, lpart);
+  hipLaunchKernelGGL(k_mlp_gsum, dim3((MLP_NTRAIN + 255) / 256), dim3(256), 0, st, gpart, lpart, nblk, grad, loss);
 }
+
+size_t mlp_partials_bytes(int64_t count) { return sizeof(float) * (size_t)(count / 32) * (MLP_NTRAIN + 1); }
 
 void mlp_adam(float *w, float *m, float *v, float *g, void *P, float lr, int t, hipStream_t st) {
   const float c1 = 1.0f - powf(0.9f, (float)t), c2 = 1.0f - powf(0.999f, (float)t);

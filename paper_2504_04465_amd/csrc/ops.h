@@ -63,6 +63,7 @@ struct Topo {
   const int32_t *xnbr;     // [Q-1][xstride] pull sources of the exception rows
   int64_t xstride;
   const double *xdu;       // [Q-1][xstride] xi_i . (inflow noise) of the rows, or null
+  int off32;               // population buffers under 4 GB: the steady-state pull uses 32-bit byte offsets
 };
 
 // the collides of every level active at a substep in one launch: what
