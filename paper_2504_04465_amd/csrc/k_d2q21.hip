@@ -36,14 +36,14 @@ __global__ void __launch_bounds__(BLOCK) k_collide_mlp(const KArgs a) {
   C rho = (C)1, u[3] = {(C)0, (C)0, (C)0}, T = (C)1;
   if (valid) {
     C f[Q], g[Q];
-    gather<L, S, PRE, true, 0, false>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[w], a.vbase, c, l, brick,
+    gather<L, S, PRE, true, 0, false>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[0], a.vbase, c, l, brick,
                             a.topo.xmask[brick], a.ph.uw, a.ph.cs2w, f, g);
     cell_moments<L, C, true>(f, g, (C)a.ph.Cv, rho, u, T);
   }
   // the populations again, after the equilibrium (no code motion across)
   auto pull = [&](C *f, C *g) {
     asm volatile("" ::: "memory");
-    gather<L, S, PRE, true, 0, false>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[w], a.vbase, c, l, brick,
+    gather<L, S, PRE, true, 0, false>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[0], a.vbase, c, l, brick,
                             a.topo.xmask[brick], a.ph.uw, a.ph.cs2w, f, g);
   };
   const bool collide = valid && !(fl & (F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ));

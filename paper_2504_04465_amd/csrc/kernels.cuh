@@ -242,11 +242,12 @@ __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnb
 // Bulk lanes: the source of population i sits in the brick at offset
 // dir = sum_d w_d 3^d (w_d = 0, 1, 2 for a step to the lower neighbour, none,
 // the upper neighbour along d) at local coordinates (lc - xi_i) mod BS.  The
-// offset of every neighbour brick (brick_unit) is staged in LDS (nbs); per
-// lane and axis the table K[d][xi_d] packs (LDS byte offset of the direction
-// part) << 16 | (byte offset of the local coordinate part), so a population
-// costs two integer adds, an LDS read, a multiply-add and a load from the
-// population's row base.
+// offset of every neighbour brick (brick_unit) is staged in LDS (nbs: the
+// block's table, [wavefront][NBP]); per lane and axis the table K[d][xi_d]
+// packs (LDS byte offset of the direction part, plus the wavefront's row in
+// K[0]) << 16 | (byte offset of the local coordinate part), so a population
+// costs two integer adds, a shift, an LDS read, a shift-or (a multiply-add
+// for buffers over 4 GB) and a load from the population's row base.
 //
 // Lanes flagged in the brick's exception mask read their explicit row:
 // every source is loaded before any is used, so the loads overlap.
@@ -268,6 +269,9 @@ __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const 
       }
       return;
     }
+    // the wavefront's row of the block's table rides in K[0], so that the
+    // LDS address of a population's neighbour brick is one shift of k
+    const uint32_t wrow = (uint32_t)(threadIdx.x >> 6) * (uint32_t)(Brick<L>::NBP * 4);
     uint32_t K[3][2 * R + 1];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -281,7 +285,8 @@ __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const 
         const int p = lc - x;
         const uint32_t w = p < 0 ? 0u : (p >= BS ? 2u : 1u);
         const uint32_t pw = d == 0 ? 1u : (d == 1 ? 3u : 9u);
-        K[d][x + R] = ((w * pw * 4u) << 16) | ((uint32_t)lane_bits<L>(p & (BS - 1), d) * (uint32_t)sizeof(S));
+        K[d][x + R] = ((w * pw * 4u + (d == 0 ? wrow : 0u)) << 16) |
+                      ((uint32_t)lane_bits<L>(p & (BS - 1), d) * (uint32_t)sizeof(S));
       }
     }
     const char *fb = (const char *)fin;
@@ -328,6 +333,9 @@ __device__ inline void push_store(S *fout, S *gout, const Topo &tp, const uint32
   Sto<S>::stn(fout, pix<L::Q>(0, c), f[0], RAW ? 0.0 : L::S.w[0]);
   if (DDF) Sto<S>::stn(gout, pix<L::Q>(0, c), g[0], 0.0);
   if (!((xm >> lane) & 1ull)) {
+    // the wavefront's row of the block's table rides in K[0], so that the
+    // LDS address of a population's neighbour brick is one shift of k
+    const uint32_t wrow = (uint32_t)(threadIdx.x >> 6) * (uint32_t)(Brick<L>::NBP * 4);
     uint32_t K[3][2 * R + 1];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -341,7 +349,8 @@ __device__ inline void push_store(S *fout, S *gout, const Topo &tp, const uint32
         const int p = lc - x;
         const uint32_t w = p < 0 ? 0u : (p >= BS ? 2u : 1u);
         const uint32_t pw = d == 0 ? 1u : (d == 1 ? 3u : 9u);
-        K[d][x + R] = ((w * pw * 4u) << 16) | ((uint32_t)lane_bits<L>(p & (BS - 1), d) * (uint32_t)sizeof(S));
+        K[d][x + R] = ((w * pw * 4u + (d == 0 ? wrow : 0u)) << 16) |
+                      ((uint32_t)lane_bits<L>(p & (BS - 1), d) * (uint32_t)sizeof(S));
       }
     }
     char *fb = (char *)fout;
@@ -1195,7 +1204,7 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
   // and the moments and the regularised populations are formed from the
   // small deviations instead of from f_i ~ w_i
   constexpr bool SH = std::is_same<S, __half>::value && COLL == COLL_RR && product_basis<L>();
-  gather<L, S, PRE || AA == 1, DDF, AA == 2 ? 2 : 0, NZ, SH, O32>(fin, gin, a.topo, nbs[threadIdx.x >> 6], a.vbase, c, threadIdx.x & 63, brick, xm,
+  gather<L, S, PRE || AA == 1, DDF, AA == 2 ? 2 : 0, NZ, SH, O32>(fin, gin, a.topo, nbs[0], a.vbase, c, threadIdx.x & 63, brick, xm,
                                                        a.ph.uw, a.ph.cs2w, f, g);
   if (!(fl & (F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ))) {
     C rho, u[3], T = (C)0, rho1 = (C)0;
@@ -1303,7 +1312,7 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
     }
   }
   if constexpr (AA == 2) {
-    push_store<L, S, DDF, SH>(fout, gout, a.topo, nbs[threadIdx.x >> 6], c, threadIdx.x & 63, brick,
+    push_store<L, S, DDF, SH>(fout, gout, a.topo, nbs[0], c, threadIdx.x & 63, brick,
                           xm, a.ph.uw, a.ph.cs2w, f, g);
   } else {
     // row base (uniform: a wavefront's brick lies in one chunk) + the
@@ -1659,7 +1668,7 @@ __global__ void __launch_bounds__(BLOCK) k_gather(const MArgs a) {
   C g[DDF ? Q : 1];
   const bool fine_ghost = valid && (a.flags[c] & F_FINE_GHOST);
   if (valid)
-    gather<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[threadIdx.x >> 6],
+    gather<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[0],
                                a.vbase, c, threadIdx.x & 63, brick, a.topo.xmask[brick], a.uw, a.cs2w, f, g);
   if (a.mode == 0) {
     if (!valid) return;
@@ -1716,7 +1725,7 @@ __global__ void __launch_bounds__(BLOCK) k_sums(const MArgs a) {
     if (cell >= 0 && !(a.flags[c] & F_FINE_GHOST)) {
       C f[Q];
       C g[DDF ? Q : 1];
-      gather<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[threadIdx.x >> 6],
+      gather<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[0],
                                  a.vbase, c, threadIdx.x & 63, brick, a.topo.xmask[brick], a.uw, a.cs2w, f, g);
       double q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -1822,7 +1831,7 @@ __global__ void __launch_bounds__(BLOCK) k_sensor(const MArgs a, const PhysArgs 
   }
   C f[Q];
   C g[DDF ? Q : 1];
-  gather<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[threadIdx.x >> 6], a.vbase,
+  gather<L, S, PRE, DDF, AA>((const S *)a.fin, (const S *)a.gin, a.topo, nbs[0], a.vbase,
                              c, threadIdx.x & 63, brick, a.topo.xmask[brick], a.uw, a.cs2w, f, g);
   C rho, u[3], T;
   cell_moments<L, C, DDF>(f, g, (C)a.Cv, rho, u, T);
