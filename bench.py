@@ -123,9 +123,9 @@ def counted_traffic(workload_name, storage):
     rocprofv3 counters and stored in the profile of this kernel and workload;
     None when there is no profile or the kernel's sources changed since."""
     import hashlib
-    if workload_name != "sphere" or storage != "fp32":
+    if workload_name != "sphere" or storage not in ("fp32", "fp16"):
         return None
-    prof = os.path.join(ROOT, "profiles", "k_collide_d3q27_rr_fp32_sphere.md")
+    prof = os.path.join(ROOT, "profiles", f"k_collide_d3q27_rr_{storage}_sphere.md")
     if not os.path.exists(prof):
         return None
     rec = None
@@ -336,12 +336,17 @@ def fp16_leg(w32, args):
     per_step = sum(int(n) << l for l, n in enumerate(s.n_per_level))
     tb = tm = 0.0
     ups = 0
+    counted = counted_traffic(w.name, "fp16")
+    ctb = 0.0
     for l in range(L):
         n_l, ms_l, bpu = s.profile_read(l)
         tb += bpu * int(s.n_per_level[l]) * n_l
         tm += ms_l
         ups += int(s.n_per_level[l]) * n_l
+        if counted is not None:
+            ctb += counted[l] * int(s.n_per_level[l]) * n_l
     s.close()
+    traffic = round(ctb / (tm * 1e-3) / 1e9, 1) if counted is not None and tm > 0 else None
     lay = tb / (tm * 1e-3) / 1e9 if tm > 0 else 0.0
     sbpu = neighbour_list_bytes_per_update(w, "fp16")
     ach = sbpu * ups / (tm * 1e-3) / 1e9 if tm > 0 else 0.0
@@ -350,7 +355,10 @@ def fp16_leg(w32, args):
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_update": sbpu,
                          "layout_bytes_per_update": round(tb / max(ups, 1), 2),
-                         "layout_achieved": round(lay, 1), "layout_frac": round(lay / HBM_PEAK_GBS, 4)}}
+                         "layout_achieved": round(lay, 1), "layout_frac": round(lay / HBM_PEAK_GBS, 4),
+                         "traffic": traffic,
+                         "traffic_frac": round(traffic / HBM_PEAK_GBS, 4) if traffic is not None else None,
+                         "traffic_bytes_per_update": round(ctb / max(ups, 1), 1) if counted is not None else None}}
 
 
 def calibrate_copy():
