@@ -1044,6 +1044,78 @@ __device__ inline void cell_moments(const C *f, const C *g, C Cv, C &rho, C (&u)
   T = DDF ? (e2 + gs - rho * uu) / ((C)2 * rho * Cv) : (C)0;
 }
 
+// index of the population with velocity (x, y, z) (z = 0 in 2-D)
+template <class L>
+__device__ constexpr int vel_index(int x, int y, int z) {
+  for (int i = 0; i < L::Q; ++i)
+    if (L::S.v[i].x == x && L::S.v[i].y == y && (L::D == 2 || L::S.v[i].z == z)) return i;
+  return -1;
+}
+
+// Moments up to second order of a product lattice (velocities {-1, 0, 1}^D)
+// of whatever f holds, by sums along one axis at a time: along x each line
+// of three populations gives f(-1) + f(0) + f(1), f(1) - f(-1) and
+// f(1) + f(-1); along y and then z only the combinations that the zeroth
+// (m0), first (j) and second (P) moments need are formed.  66 additions for
+// D3Q27 instead of the 170 of one running sum per moment.
+template <class L, class C>
+__device__ inline void moments_product(const C *f, C &m0, C (&j)[3], C (&P)[3][3]) {
+  constexpr int NZ = L::D == 3 ? 3 : 1;
+  C s0[3][NZ], s1[3][NZ], s2[3][NZ];
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int c = 0; c < NZ; ++c) {
+      const int z = L::D == 3 ? c - 1 : 0;
+      const C lo = f[vel_index<L>(-1, b - 1, z)], mid = f[vel_index<L>(0, b - 1, z)], hi = f[vel_index<L>(1, b - 1, z)];
+      s2[b][c] = hi + lo;
+      s1[b][c] = hi - lo;
+      s0[b][c] = s2[b][c] + mid;
+    }
+  // along y: t_ab[c] = sum over y of xi_x^a xi_y^b (per z line)
+  C t00[NZ], t01[NZ], t02[NZ], t10[NZ], t11[NZ], t20[NZ];
+#pragma unroll
+  for (int c = 0; c < NZ; ++c) {
+    t02[c] = s0[2][c] + s0[0][c];
+    t00[c] = t02[c] + s0[1][c];
+    t01[c] = s0[2][c] - s0[0][c];
+    t10[c] = (s1[2][c] + s1[0][c]) + s1[1][c];
+    t11[c] = s1[2][c] - s1[0][c];
+    t20[c] = (s2[2][c] + s2[0][c]) + s2[1][c];
+  }
+  C m001 = (C)0, m002 = (C)0, m011 = (C)0, m101 = (C)0;
+  C m000, m010, m020, m100, m110, m200;
+  if constexpr (L::D == 3) {
+    m002 = t00[2] + t00[0];
+    m000 = m002 + t00[1];
+    m001 = t00[2] - t00[0];
+    m010 = (t01[2] + t01[0]) + t01[1];
+    m011 = t01[2] - t01[0];
+    m020 = (t02[2] + t02[0]) + t02[1];
+    m100 = (t10[2] + t10[0]) + t10[1];
+    m101 = t10[2] - t10[0];
+    m110 = (t11[2] + t11[0]) + t11[1];
+    m200 = (t20[2] + t20[0]) + t20[1];
+  } else {
+    m000 = t00[0];
+    m010 = t01[0];
+    m020 = t02[0];
+    m100 = t10[0];
+    m110 = t11[0];
+    m200 = t20[0];
+  }
+  m0 = m000;
+  j[0] = m100;
+  j[1] = m010;
+  j[2] = m001;
+  P[0][0] = m200;
+  P[1][1] = m020;
+  P[2][2] = m002;
+  P[0][1] = P[1][0] = m110;
+  P[0][2] = P[2][0] = m101;
+  P[1][2] = P[2][1] = m011;
+}
+
 // the same from h_i = f_i - w_i (single distribution): rho1 = sum h_i is
 // rho - 1 without rounding against 1; sum w_i xi_i = 0 leaves j unchanged
 template <class L, class C>
@@ -1208,8 +1280,27 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
                                                        a.ph.uw, a.ph.cs2w, f, g);
   if (!(fl & (F_FINE_GHOST | F_BC_NEUMANN | F_BC_EQ))) {
     C rho, u[3], T = (C)0, rho1 = (C)0;
-    if constexpr (SH) cell_moments_shifted<L, C>(f, rho1, rho, u);
-    else cell_moments<L, C, DDF>(f, g, (C)a.ph.Cv, rho, u, T);
+    // recursive regularisation on a product lattice takes its moments, the
+    // second-order ones included, from moments_product
+    constexpr bool PM = COLL == COLL_RR && product_basis<L>();
+    C P[3][3];
+    if constexpr (PM) {
+      C m0, j[3];
+      moments_product<L, C>(f, m0, j, P);
+      if constexpr (SH) {
+        rho1 = m0;
+        rho = (C)1 + rho1;
+      } else {
+        rho = m0;
+      }
+      const C inv = (C)1 / rho;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) u[d] = d < L::D ? j[d] * inv : (C)0;
+    } else if constexpr (SH) {
+      cell_moments_shifted<L, C>(f, rho1, rho, u);
+    } else {
+      cell_moments<L, C, DDF>(f, g, (C)a.ph.Cv, rho, u, T);
+    }
     C rhop = rho, rhop1 = rho1;
     if (fl & F_SPONGE) {
       const C s = (C)a.sigma[c];
@@ -1225,24 +1316,25 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
 #pragma unroll
       for (int i = 0; i < Q; ++i) f[i] = f[i] - om * (f[i] - feq[i]);
     } else if constexpr (COLL == COLL_RR) {
-      C P[3][3];
+      if constexpr (!PM) {
 #pragma unroll
-      for (int x = 0; x < 3; ++x)
+        for (int x = 0; x < 3; ++x)
 #pragma unroll
-        for (int y = 0; y < 3; ++y) P[x][y] = (C)0;
+          for (int y = 0; y < 3; ++y) P[x][y] = (C)0;
 #pragma unroll
-      for (int i = 0; i < Q; ++i)
+        for (int i = 0; i < Q; ++i)
+#pragma unroll
+          for (int x = 0; x < L::D; ++x)
+#pragma unroll
+            for (int y = x; y < L::D; ++y) {
+              const int cc = cx_<L>(i, x) * cx_<L>(i, y);
+              if (cc != 0) P[x][y] += (C)cc * f[i];
+            }
 #pragma unroll
         for (int x = 0; x < L::D; ++x)
 #pragma unroll
-          for (int y = x; y < L::D; ++y) {
-            const int cc = cx_<L>(i, x) * cx_<L>(i, y);
-            if (cc != 0) P[x][y] += (C)cc * f[i];
-          }
-#pragma unroll
-      for (int x = 0; x < L::D; ++x)
-#pragma unroll
-        for (int y = 0; y < x; ++y) P[x][y] = P[y][x];
+          for (int y = 0; y < x; ++y) P[x][y] = P[y][x];
+      }
       if constexpr (product_basis<L>())
         rr_product<L, C, SH>(f, rho, rhop, u, P, (C)krr, a.ph.trace_eq != 0, rho1, rhop1);
       else
