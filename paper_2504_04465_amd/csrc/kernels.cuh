@@ -1198,14 +1198,15 @@ struct MinWaves {
   static constexpr int value = COLL < COLL_DDF_POLY ? (sizeof(S) == 8 ? 4 : 6) : (COLL >= COLL_DDF_NEWTON ? 2 : 1);
 };
 
-// Block size of the collide kernel: in 3-D one block is the 2 x 2 x 2 cube
-// of bricks that is consecutive in Z order; the barrier after the table
-// staging releases its eight wavefronts together, so their pulls from each
-// other's bricks meet in the L2 (1 % faster than four bricks per block on
-// the sphere; in 2-D four bricks are better).
+// Block size of the collide kernel: four bricks (256 threads) on every
+// lattice.  With the chunked population layout this beats the 2 x 2 x 2
+// cube of bricks that is consecutive in Z order (512 threads; sphere FP16
+// +7.6 %, FP32 +0.9 %) and two or one bricks per block (-2 to -4 %; in 2-D
+// two bricks cost 1-3 %); the cube was 1 % ahead while each population had
+// a row of the whole buffer.
 template <class L, int COLL>
 struct CollideBlock {
-  static constexpr int value = (L::D == 3 && COLL < COLL_DDF_POLY) ? 512 : BLOCK;
+  static constexpr int value = BLOCK;
 };
 
 // AA selects in-place streaming on one buffer (a.fin == a.fout): 1 = even
