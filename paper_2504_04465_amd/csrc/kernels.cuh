@@ -1419,8 +1419,15 @@ __global__ void __launch_bounds__((CollideBlock<L, COLL>::value))
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int64_t r = AA == 1 ? L::S.opp[i] : i;
-      Sto<S>::stp((S *)(ob + r * rbytes + co), f[i], SH ? 0.0 : L::S.w[i]);
-      if (DDF) Sto<S>::stp((S *)(gb + r * rbytes + co), g[i], 0.0);
+      // the row base stays uniform (SGPRs) and the store adds the offset
+      auto row = (gptr<char>)(ob + r * rbytes);
+      asm("" : "+s"(row));
+      Sto<S>::stg((gptr<S>)(row + co), f[i], SH ? 0.0 : L::S.w[i]);
+      if (DDF) {
+        auto grow = (gptr<char>)(gb + r * rbytes);
+        asm("" : "+s"(grow));
+        Sto<S>::stg((gptr<S>)(grow + co), g[i], 0.0);
+      }
     }
   }
 }
