@@ -64,7 +64,7 @@ struct lbm_ctx {
   int dim = 0, L = 0;
   double tau[8]{};
   double bpu[8]{};  // algorithmic bytes per cell update of the collide kernel, per level
-  int64_t N = 0, NS = 0, Ng = 0, stride = 0;  // cells, slots, coarse ghosts, SoA stride
+  int64_t N = 0, NS = 0, Ng = 0, stride = 0;  // cells, slots, coarse ghosts, slots per population buffer
   // device
   std::vector<void *> allocs;
   void *f[2]{}, *gb[2]{};
