@@ -250,7 +250,12 @@ __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnb
 // for buffers over 4 GB) and a load from the population's row base.
 //
 // Lanes flagged in the brick's exception mask read their explicit row:
-// every source is loaded before any is used, so the loads overlap.
+// every source is loaded before any is used, so the loads overlap.  In a
+// two-buffer pull (not PRE, AA = 0) they take the bulk addresses with the
+// other lanes first and read the row only for the populations whose source
+// differs (clear bits of the row's regular-pull mask), so the wavefront
+// does not run a second, serial gather for them.
+// nbs must be a staged table: gather_one reads exception rows itself.
 template <class L, class S, bool PRE, bool DDF, int AA = 0, bool NZ = true, bool RAW = false, bool O32 = false>
 __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const uint32_t *nbs, int64_t vbase, int64_t c, int lane, int32_t brick, uint64_t xm,
                               const double (&uw)[6][3], double cs2w, typename Sto<S>::C *f,
@@ -260,7 +265,9 @@ __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const 
   const int64_t c0 = pix<L::Q>(0, c);
   f[0] = RAW ? Sto<S>::ldr(fin[c0]) : Sto<S>::ld(fin, c0, L::S.w[0]);
   if (DDF) g[0] = Sto<S>::ld(gin, c0, 0.0);
-  if (!((xm >> lane) & 1ull)) {
+  constexpr bool UNI = !PRE && AA == 0;
+  const bool ex = (xm >> lane) & 1ull;
+  if (UNI || !ex) {
     if (PRE) {
 #pragma unroll
       for (int i = 1; i < L::Q; ++i) {
@@ -312,10 +319,11 @@ __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const 
         }
       }
     }
-  } else {
+  }
+  if (ex) {
     const int64_t row = tp.xbase[brick] + __popcll(xm & ((1ull << lane) - 1ull));
     gather_row<L, S, PRE, DDF, AA, NZ, RAW>(fin, gin, tp.xnbr, tp.xstride, row, vbase, c, uw, cs2w, f, g,
-                                            ~0ull, tp.xdu);
+                                            UNI ? ~tp.xreg[row] : ~0ull, tp.xdu);
   }
 }
 
@@ -411,12 +419,13 @@ __device__ inline void gather_one(const S *fin, const S *gin, const Topo &tp, in
   const int64_t brick = c >> 6;
   const int lane = (int)(c & 63);
   const uint64_t xm = tp.xmask[brick];
-  if ((xm >> lane) & 1ull) {
-    gather<L, S, PRE, DDF, AA>(fin, gin, tp, nullptr, vbase, c, lane, (int32_t)brick, xm, uw, cs2w, f, g);
-    return;
-  }
   f[0] = Sto<S>::ld(fin, pix<L::Q>(0, c), L::S.w[0]);
   if (DDF) g[0] = Sto<S>::ld(gin, pix<L::Q>(0, c), 0.0);
+  if ((xm >> lane) & 1ull) {
+    const int64_t row = tp.xbase[brick] + __popcll(xm & ((1ull << lane) - 1ull));
+    gather_row<L, S, PRE, DDF, AA>(fin, gin, tp.xnbr, tp.xstride, row, vbase, c, uw, cs2w, f, g, ~0ull, tp.xdu);
+    return;
+  }
 #pragma unroll
   for (int i = 1; i < L::Q; ++i) {
     int64_t src = c;

@@ -204,4 +204,36 @@ int build_layout(const HostGrid &g, const LatticeInfo &lat, const bool periodic[
   return 0;
 }
 
+void regular_pulls(const DeviceLayout &y, const LatticeInfo &lat, std::vector<uint64_t> *out) {
+  const int D = y.D, sh = y.sh, bs = y.bs, Qm = lat.Q - 1;
+  const int64_t nbrk = (int64_t)y.xmask.size();
+  out->assign((size_t)std::max<int64_t>(y.nx, 1), 0ull);
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t b = 0; b < nbrk; ++b) {
+    int64_t row = y.xbase[b];
+    for (uint64_t m = y.xmask[b]; m; m &= m - 1, ++row) {
+      const int lane = __builtin_ctzll(m);
+      int lc[3] = {0, 0, 0};
+      for (int k = 0; k < sh; ++k)
+        for (int a = 0; a < D; ++a) lc[a] |= ((lane >> (D * k + a)) & 1) << k;
+      uint64_t bits = 0;
+      for (int i = 1; i <= Qm; ++i) {
+        int dir = 0, pw = 1, q[3] = {0, 0, 0};
+        for (int a = 0; a < D; ++a) {
+          const int64_t p = lc[a] - lat.c[i][a];
+          const int64_t w = floordiv(p, bs);
+          q[a] = (int)(p - w * bs);
+          dir += (int)(w + 1) * pw;
+          pw *= 3;
+        }
+        const int32_t nb = y.nbrick[(size_t)b * y.nbp + dir];
+        if (nb >= 0 && (int64_t)y.xnbr[(size_t)(i - 1) * y.xstride + row] ==
+                           (int64_t)nb * 64 + brick_local(D, sh, q[0], q[1], q[2]))
+          bits |= 1ull << i;
+      }
+      (*out)[row] = bits;
+    }
+  }
+}
+
 }  // namespace lbm

@@ -41,6 +41,12 @@ struct DeviceLayout {
   std::vector<int32_t> xnbr;
 };
 
+// Per exception row, bit i set where population i pulls from the slot the
+// bulk gather's brick arithmetic gives (the neighbour brick of its direction,
+// at the local coordinates wrapped into it): a two-buffer pull takes that
+// address for the row's cell and reads the explicit source of the others only.
+void regular_pulls(const DeviceLayout &y, const LatticeInfo &lat, std::vector<uint64_t> *out);
+
 // periodic[a]: axis a wraps.  Returns 0 or -1 (*err set).
 int build_layout(const HostGrid &g, const LatticeInfo &lat, const bool periodic[3], DeviceLayout *out,
                  std::string *err);

@@ -70,7 +70,7 @@ struct lbm_ctx {
   void *f[2]{}, *gb[2]{};
   int32_t *d_nbrick = nullptr, *d_xbase = nullptr, *d_xnbr = nullptr;
   double *d_xdu = nullptr;  // xi_i . inflow noise per explicit row [Q-1][xstride], or null
-  uint64_t *d_xmask = nullptr;
+  uint64_t *d_xmask = nullptr, *d_xreg = nullptr;
   int32_t *d_cell_of = nullptr, *d_slot_of = nullptr, *d_crow = nullptr;
   uint8_t *d_flags = nullptr;
   double *d_sigma = nullptr, *d_rhoinf = nullptr;
@@ -155,7 +155,7 @@ void free_device(lbm_ctx *c) {
   c->f[0] = c->f[1] = c->gb[0] = c->gb[1] = nullptr;
   c->d_nbrick = c->d_xbase = c->d_xnbr = nullptr;
   c->d_xdu = nullptr;
-  c->d_xmask = nullptr;
+  c->d_xmask = c->d_xreg = nullptr;
   c->d_cell_of = c->d_slot_of = c->d_crow = nullptr;
   c->d_flags = nullptr;
   c->d_gslot = nullptr;
@@ -243,6 +243,7 @@ Topo topo(const lbm_ctx *c) {
   t.xmask = c->d_xmask;
   t.xbase = c->d_xbase;
   t.xnbr = c->d_xnbr;
+  t.xreg = c->d_xreg;
   t.xstride = c->lay.xstride;
   t.xdu = c->d_xdu;
   t.off32 = (double)c->ops.sizeof_storage * c->lat.Q * (double)c->stride < 4294967296.0;
@@ -728,6 +729,11 @@ lbm_status lbm_grid_build(lbm_ctx *c, int dim, const int32_t ext[3], int n_level
   if ((s = upload(c, &c->d_xmask, y.xmask.data(), y.xmask.size())) != LBM_OK) return s;
   if ((s = upload(c, &c->d_xbase, y.xbase.data(), y.xbase.size())) != LBM_OK) return s;
   if ((s = upload(c, &c->d_xnbr, y.xnbr.data(), y.xnbr.size())) != LBM_OK) return s;
+  {
+    std::vector<uint64_t> xreg;
+    regular_pulls(y, c->lat, &xreg);
+    if ((s = upload(c, &c->d_xreg, xreg.data(), xreg.size())) != LBM_OK) return s;
+  }
   if ((s = upload(c, &c->d_cell_of, y.cell_of.data(), y.cell_of.size())) != LBM_OK) return s;
   if (c->dg.slot_of) c->d_slot_of = c->dg.slot_of;
   else if ((s = upload(c, &c->d_slot_of, y.slot_of.data(), y.slot_of.size())) != LBM_OK) return s;

@@ -61,6 +61,7 @@ struct Topo {
   const uint64_t *xmask;   // [bricks] lanes with an exception row
   const int32_t *xbase;    // [bricks] first exception row of the brick
   const int32_t *xnbr;     // [Q-1][xstride] pull sources of the exception rows
+  const uint64_t *xreg;    // [rows] bit i: the row's source of population i is the bulk gather's
   int64_t xstride;
   const double *xdu;       // [Q-1][xstride] xi_i . (inflow noise) of the rows, or null
   int off32;               // population buffers under 4 GB: the steady-state pull uses 32-bit byte offsets
