@@ -251,10 +251,13 @@ __device__ inline void gather_row(const S *fin, const S *gin, const int32_t *xnb
 //
 // Lanes flagged in the brick's exception mask read their explicit row:
 // every source is loaded before any is used, so the loads overlap.  In a
-// two-buffer pull (not PRE, AA = 0) they take the bulk addresses with the
-// other lanes first and read the row only for the populations whose source
-// differs (clear bits of the row's regular-pull mask), so the wavefront
-// does not run a second, serial gather for them.
+// two-buffer pull (not PRE, AA = 0) on a nearest-neighbour lattice they
+// take the bulk addresses with the other lanes first and read the row only
+// for the populations whose source differs (clear bits of the row's
+// regular-pull mask), so the wavefront does not run a second, serial
+// gather for them.  The multi-speed lattices keep the split: there the
+// bulk values held across the row reads cost registers (D2Q37: 167 -> 193
+// VGPRs, one wavefront per SIMD fewer) and time.
 // nbs must be a staged table: gather_one reads exception rows itself.
 template <class L, class S, bool PRE, bool DDF, int AA = 0, bool NZ = true, bool RAW = false, bool O32 = false>
 __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const uint32_t *nbs, int64_t vbase, int64_t c, int lane, int32_t brick, uint64_t xm,
@@ -265,7 +268,7 @@ __device__ inline void gather(const S *fin, const S *gin, const Topo &tp, const 
   const int64_t c0 = pix<L::Q>(0, c);
   f[0] = RAW ? Sto<S>::ldr(fin[c0]) : Sto<S>::ld(fin, c0, L::S.w[0]);
   if (DDF) g[0] = Sto<S>::ld(gin, c0, 0.0);
-  constexpr bool UNI = !PRE && AA == 0;
+  constexpr bool UNI = !PRE && AA == 0 && L::B == 1;
   const bool ex = (xm >> lane) & 1ull;
   if (UNI || !ex) {
     if (PRE) {
